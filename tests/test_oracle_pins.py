@@ -1,0 +1,463 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test ties one part of the oracle to something other than the oracle
+itself: closed-form chords, exact quadrature of affine fields, the midpoint
+rule's error bounds for ellipsoid and Gaussian phantoms (exact line integrals
+computed here), special networks whose output is known in closed form,
+central finite differences of the oracle's own forward pass for its
+hand-written reverse mode, batch additivity of Eq. (5)/(8), the first Adam
+step, and the parameter count printed in the paper.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_19075_amd import synth as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def geom_parallel(rows=33, cols=33, n_views=4, span=math.pi, fov_kind=0, fov=None, pitch=3.0 / 32):
+    th = np.arange(n_views) * span / n_views
+    tt = np.arange(n_views) / n_views
+    return S.Geometry(kind=0, rows=rows, cols=cols, n_views=n_views, fov_kind=fov_kind,
+                      pitch_u=pitch, pitch_v=pitch,
+                      fov=fov if fov is not None else (-1, 1, -1, 1, -1, 1), theta=th, time=tt)
+
+
+def geom_cone(rows=33, cols=33, n_views=4):
+    th = np.arange(n_views) * 2 * math.pi / n_views
+    tt = np.arange(n_views) / n_views
+    return S.Geometry(kind=1, rows=rows, cols=cols, n_views=n_views, sod=500.0, sdd=1000.0,
+                      pitch_u=3.0 / 32, pitch_v=3.0 / 32, theta=th, time=tt)
+
+
+def centre_index(g, m=0):
+    return m * g.rows * g.cols + (g.rows // 2) * g.cols + g.cols // 2
+
+
+# ------------------------------------------------------------------ geometry
+
+def test_central_parallel_ray_box_chord():
+    g = geom_parallel()
+    o, d, t = O.ray(g, centre_index(g, 0))
+    np.testing.assert_allclose(o, [0, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(d, [1, 0, 0], atol=1e-15)
+    s_in, ln = O.clip(g, o, d)
+    assert s_in == -1.0 and ln == 2.0
+
+
+def test_diagonal_parallel_ray_chord():
+    g = geom_parallel(n_views=4, span=math.pi)  # view 1 at 45 degrees
+    o, d, t = O.ray(g, centre_index(g, 1))
+    np.testing.assert_allclose(d, [math.cos(math.pi / 4), -math.sin(math.pi / 4), 0], atol=1e-15)
+    s_in, ln = O.clip(g, o, d)
+    assert abs(ln - 2 * math.sqrt(2)) < 1e-14
+    assert abs(t - 0.25) < 1e-15
+
+
+def test_rotation_sign_convention():
+    """Object rotation by theta = source/detector rotation by -theta (Sec. II):
+    at theta = 90 deg the +x ray direction maps to -y, and the detector u
+    axis (+y at 0 deg) maps to +x."""
+    g = geom_parallel(n_views=2, span=math.pi)  # view 1 at 90 degrees
+    i = 1 * g.rows * g.cols + (g.rows // 2) * g.cols + (g.cols // 2 + 3)  # u = 3 pitch
+    o, d, _ = O.ray(g, i)
+    np.testing.assert_allclose(d, [0, -1, 0], atol=1e-15)
+    np.testing.assert_allclose(o, [3 * g.pitch_u, 0, 0], atol=1e-15)
+
+
+def test_cylinder_chord_closed_form():
+    g = geom_parallel(fov_kind=1, fov=(0.8, -0.5, 0.5, 0, 0, 0))
+    for k in [0, 3, 7]:
+        i = (g.rows // 2) * g.cols + g.cols // 2 + k
+        o, d, _ = O.ray(g, i)
+        u = k * g.pitch_u
+        s_in, ln = O.clip(g, o, d)
+        assert abs(ln - 2 * math.sqrt(0.8 ** 2 - u ** 2)) < 1e-14
+        assert abs(s_in + math.sqrt(0.8 ** 2 - u ** 2)) < 1e-14
+    # outside the z slab: miss
+    i = (g.rows // 2 + 8) * g.cols + g.cols // 2  # v = 8 pitch = 0.75 > 0.5
+    o, d, _ = O.ray(g, i)
+    assert O.clip(g, o, d)[1] == 0.0
+
+
+def test_cone_central_ray_and_magnification():
+    g = geom_cone()
+    o, d, _ = O.ray(g, centre_index(g))
+    np.testing.assert_allclose(o, [-500, 0, 0], atol=1e-12)
+    s_in, ln = O.clip(g, o, d)
+    assert abs(s_in - 499.0) < 1e-12 and abs(ln - 2.0) < 1e-12
+    # a ray to detector offset u crosses x = 0 at u * SOD / SDD
+    k = 5
+    o, d, _ = O.ray(g, centre_index(g) + k)
+    s0 = -o[0] / d[0]
+    assert abs((o + s0 * d)[1] - k * g.pitch_u * 500.0 / 1000.0) < 1e-12
+
+
+def test_oracle_rays_match_scanner_rays():
+    """Two separately written ray constructions of the stated convention."""
+    for g in (S.workload("c0").geom, S.workload("c3").geom):
+        rng = np.random.default_rng(0)
+        idx = rng.integers(0, g.n_proj, 300)
+        so, sd, st = S.scanner_rays(g, idx)
+        ssi, sln = S.scanner_fov_chord(g, so, sd)
+        for k, i in enumerate(idx):
+            o, d, t = O.ray(g, int(i))
+            np.testing.assert_allclose(o, so[k], atol=1e-12)
+            np.testing.assert_allclose(d, sd[k], atol=1e-15)
+            assert t == st[k]
+            si, ln = O.clip(g, o, d)
+            assert abs(ln - sln[k]) < 1e-12
+            if ln > 0:
+                assert abs(si - ssi[k]) < 1e-12
+
+
+def test_sample_counts():
+    sp = S.Sampling(mode=1, h=1.0 / 256, n_min=32, n_max=512)
+    assert O.nsamp(sp, 2.0) == 512
+    assert O.nsamp(sp, 1.0) == 256
+    assert O.nsamp(sp, 1.0 + 1e-9) == 257
+    assert O.nsamp(sp, 0.01) == 32
+    assert O.nsamp(sp, 3.4) == 512
+    assert O.nsamp(sp, 0.0) == 0
+    assert O.nsamp(S.Sampling(mode=0, n=64), 0.5) == 64
+
+
+def test_normalisation():
+    g = geom_parallel(fov=(-2, 2, 0, 1, -1, 3))
+    g.t0, g.t1 = 0.0, 2.0
+    r = O.normalize(g, [1.0, 0.25, 2.0], 0.5)
+    np.testing.assert_allclose(r, [-0.5, 0.5, -0.5, 0.5], atol=1e-15)  # (t, z, y, x)
+
+
+# --------------------------------------------------------- forward model
+
+def affine_closed_form(g, idx, coef, mu0):
+    """mu0 * l * M(chord midpoint): the midpoint rule integrates an affine field
+    exactly."""
+    o, d, t = S.scanner_rays(g, idx)
+    s_in, ln = S.scanner_fov_chord(g, o, d)
+    mid = o + (s_in + 0.5 * ln)[:, None] * d
+    lo = np.array(g.fov[0::2])
+    hi = np.array(g.fov[1::2])
+    xb = 2 * (mid - lo) / (hi - lo) - 1
+    tb = 2 * (t - g.t0) / (g.t1 - g.t0) - 1
+    a0, at, az, ay, ax = coef
+    return mu0 * ln * (a0 + at * tb + az * xb[:, 2] + ay * xb[:, 1] + ax * xb[:, 0])
+
+
+@pytest.mark.parametrize("maker,n", [(lambda: S.workload("c0").geom, 7),
+                                     (lambda: S.workload("c3").geom, 64)])
+def test_affine_field_exact(maker, n):
+    g = maker()
+    m = S.MLPSpec(mu0=1.7)
+    coef = (0.3, -0.2, 0.45, 0.7, -1.1)
+    idx = S.draw_rays(g, 200, seed=5)
+    proj, nn, _, ln = O.forward(g, m, S.Sampling(mode=0, n=n), None, None, idx, field=(1, coef))
+    ref = affine_closed_form(g, idx, coef, m.mu0)
+    assert np.all(nn == n)
+    np.testing.assert_allclose(proj, ref, rtol=0, atol=1e-12)
+
+
+def test_ellipsoid_phantom_midpoint_bound_and_convergence():
+    w = S.workload("c0")
+    ph = S.make_phantom(w)
+    m = S.MLPSpec(mu0=0.8)
+    idx = S.draw_rays(w.geom, 400, seed=9)
+    exact = S.project_phantom(w.geom, ph, idx)
+    o, d, t = S.scanner_rays(w.geom, idx)
+    _, ln = S.scanner_fov_chord(w.geom, o, d)
+    hit = S.ellipsoid_chords(ph, o, d, t) > 0
+    errs = []
+    for n in (16, 64, 256):
+        proj, _, _, _ = O.forward(w.geom, m, S.Sampling(mode=0, n=n), None, None, idx,
+                                  field=(2, ph.packed()))
+        h = ln / n
+        bound = h * (hit * ph.a[None, :]).sum(axis=1)
+        assert np.all(np.abs(proj - exact) <= bound + 1e-12)
+        errs.append(np.abs(proj - exact).mean())
+    assert errs[0] > errs[1] > errs[2]
+    assert np.count_nonzero(exact) > 20
+
+
+def gaussian_line_integral(o, d, s_in, ln, c, sig, a):
+    """Exact integral of a exp(-|o + s d - c|^2 / 2 sig^2) over [s_in, s_in+ln]."""
+    s_star = np.sum((c - o) * d, axis=1)
+    perp2 = np.sum((o + s_star[:, None] * d - c) ** 2, axis=1)
+    from scipy.special import erf
+    k = math.sqrt(2.0) * sig
+    return a * np.exp(-perp2 / (2 * sig * sig)) * sig * math.sqrt(math.pi / 2) * (
+        erf((s_in + ln - s_star) / k) - erf((s_in - s_star) / k))
+
+
+def test_gaussian_blob_second_order():
+    g = geom_parallel(rows=17, cols=17, n_views=3)
+    c0 = np.array([0.1, -0.2, 0.05])
+    vel = np.array([0.1, 0.05, -0.1])
+    sig, a = 0.35, 0.9
+    m = S.MLPSpec(mu0=1.0)
+    idx = S.draw_rays(g, 150, seed=2)
+    o, d, t = S.scanner_rays(g, idx)
+    s_in, ln = S.scanner_fov_chord(g, o, d)
+    exact = gaussian_line_integral(o, d, s_in, ln, c0[None, :] + vel[None, :] * t[:, None], sig, a)
+    blob = np.concatenate([c0, vel, [sig, a]])[None, :]
+    prev = None
+    for n in (8, 16, 32):
+        proj, _, _, _ = O.forward(g, m, S.Sampling(mode=0, n=n), None, None, idx, field=(3, blob))
+        h = ln / n
+        bound = ln * h * h * a / (24 * sig * sig)  # (b-a) h^2 max|f''| / 24, max|f''| <= a/sig^2
+        err = np.abs(proj - exact)
+        assert np.all(err <= bound + 1e-13)
+        if prev is not None:
+            assert err.max() < prev / 3.0
+        prev = err.max()
+
+
+def test_ray_missing_fov_gives_zero():
+    g = geom_parallel(rows=33, cols=33, pitch=0.1)  # outer pixels at |v| = 1.6 miss the box
+    idx = np.array([0, 5, g.cols - 1])
+    m = S.MLPSpec(n_freq=2, width=4, depth=2)
+    B = S.make_B(m, 0)
+    P = S.make_params(m, 0)
+    proj, n, _, ln = O.forward(g, m, S.Sampling(mode=0, n=8), B, P, idx)
+    assert np.all(ln == 0) and np.all(n == 0) and np.all(proj == 0)
+    loss, grad, _ = O.step(g, m, S.Sampling(mode=0, n=8), B, P, idx,
+                           np.array([1.0, 2.0, 0.5]))
+    assert abs(loss - (1 + 4 + 0.25) / 3) < 1e-15 and np.all(grad == 0)
+
+
+# ------------------------------------------------------------- the network
+
+def path_network(C, H, L, a, b, mu0=1.0, act=0, bias1=1.0, out_bias=-1.0):
+    """A network whose only path takes encoding feature b through hidden unit a
+    of every layer: W1 = e_a e_b^T, b1 = bias1 e_a, identity for layers 2..L,
+    w_o = e_a, b_o = out_bias, identity output.  With ReLU and bias1 >= 1 the
+    output is exactly phi_b + bias1 + out_bias."""
+    m = S.MLPSpec(n_freq=C, width=H, depth=L, act=act, out_act=0, mu0=mu0)
+    parts = []
+    W1 = np.zeros((H, 2 * C)); W1[a, b] = 1.0
+    b1 = np.zeros(H); b1[a] = bias1
+    parts += [W1.ravel(), b1]
+    for _ in range(L - 1):
+        parts += [np.eye(H).ravel(), np.zeros(H)]
+    wo = np.zeros(H); wo[a] = 1.0
+    parts += [wo, [out_bias]]
+    return m, np.concatenate(parts)
+
+
+@pytest.mark.parametrize("col", [0, 1, 2, 3])
+@pytest.mark.parametrize("which", ["cos", "sin"])
+def test_grff_feature_order_and_B_columns(col, which):
+    """B row = e_col / 4 makes feature c equal cos(pi q/2) (or sin for c + C)
+    of the col-th normalised coordinate in the order (t, z, y, x)."""
+    C, H, L = 3, 5, 3
+    rowsel = 1
+    B = np.zeros((C, 4)); B[rowsel, col] = 0.25
+    feat = rowsel if which == "cos" else C + rowsel
+    m, P = path_network(C, H, L, a=2, b=feat, mu0=1.3)
+    g = geom_parallel(fov=(-2, 2, -1, 3, 0, 1))
+    rng = np.random.default_rng(col)
+    pts = np.column_stack([rng.uniform(-2, 2, 20), rng.uniform(-1, 3, 20), rng.uniform(0, 1, 20),
+                           rng.uniform(0, 1, 20)])
+    out = O.field_points(g, m, B, P, pts)
+    nb = np.column_stack([2 * pts[:, 3] - 1, 2 * pts[:, 2] - 1, (pts[:, 1] + 1) / 2 - 1,
+                          (pts[:, 0] + 2) / 2 - 1])  # (t, z, y, x)
+    q = nb[:, col]
+    f = np.cos(np.pi * q / 2) if which == "cos" else np.sin(np.pi * q / 2)
+    np.testing.assert_allclose(out, m.mu0 * f, atol=1e-14)
+
+
+def test_softplus_and_swish_special_values():
+    C, H, L = 2, 3, 2
+    g = geom_parallel()
+    pts = np.array([[0.1, 0.2, 0.3, 0.4]])
+    # all-zero network: M = softplus(0) = ln 2
+    m = S.MLPSpec(n_freq=C, width=H, depth=L, act=0, out_act=1)
+    P = np.zeros(m.n_params)
+    out = O.field_points(g, m, np.zeros((C, 4)), P, pts)
+    assert abs(out[0] - math.log(2)) < 1e-15
+    # swish: W = 0, b1 = 1 -> h1 = swish(1); layer 2 identity, b2 = 0 -> h2 = swish(swish(1))
+    m = S.MLPSpec(n_freq=C, width=H, depth=L, act=1, out_act=0)
+    P = np.concatenate([np.zeros(H * 2 * C), np.ones(H), np.eye(H).ravel(), np.zeros(H),
+                        np.ones(H), [0.0]])
+    out = O.field_points(g, m, np.zeros((C, 4)), P, pts)
+    s1 = 1.0 / (1.0 + math.exp(-1.0))
+    s2 = s1 / (1.0 + math.exp(-s1))
+    assert abs(out[0] - 3 * s2) < 1e-15
+    # softplus far from 0 in both directions
+    m = S.MLPSpec(n_freq=C, width=H, depth=L, act=0, out_act=1)
+    for bo, ref in [(40.0, 40.0 + math.log1p(math.exp(-40.0))), (-40.0, math.log1p(math.exp(-40.0)))]:
+        P = np.zeros(m.n_params); P[-1] = bo
+        out = O.field_points(g, m, np.zeros((C, 4)), P, pts)
+        assert abs(out[0] - ref) <= 1e-15 * max(1.0, abs(ref))
+
+
+def test_weight_matrix_is_out_by_in():
+    """A non-square first layer with one entry W1[a, b]: only unit a sees
+    feature b (a transposed read would need b < H and pick another unit)."""
+    C, H, L = 4, 3, 1
+    B = np.zeros((C, 4)); B[:, 3] = [0.05, 0.1, 0.15, 0.2]
+    g = geom_parallel()
+    pts = np.array([[0.3, 0.0, 0.0, 0.5]])
+    xb = 0.3
+    for a, b in [(0, 5), (2, 1), (1, 7)]:
+        m, P = path_network(C, H, L, a=a, b=b)
+        out = O.field_points(g, m, B, P, pts)
+        phi = np.concatenate([np.cos(2 * np.pi * B[:, 3] * xb), np.sin(2 * np.pi * B[:, 3] * xb)])
+        assert abs(out[0] - phi[b]) < 1e-14
+
+
+def test_param_count_matches_paper():
+    """The paper's network (2C = 256, L = 5) has the parameter count its
+    compression statement is computed from (golden fixture)."""
+    with open(os.path.join(GOLDEN, "paper_param_count.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    for C, H, L, count in rows:
+        m = S.MLPSpec(n_freq=int(C), width=int(H), depth=int(L))
+        assert O.nparams(m) == int(count) == m.n_params
+
+
+# -------------------------------------------------------------- gradient
+
+def tiny_case(act=1, out_act=1, R=6, n=5, seed=0, C=3, H=6, L=3):
+    g = geom_parallel(rows=9, cols=9, n_views=5, pitch=0.3)
+    m = S.MLPSpec(n_freq=C, width=H, depth=L, act=act, out_act=out_act, mu0=0.9,
+                  sigma_t=1.0, sigma_s=1.5)
+    B = S.make_B(m, seed).astype(np.float64)
+    P = S.make_params(m, seed + 1).astype(np.float64)
+    idx = S.draw_rays(g, R, seed + 2)
+    meas = np.random.default_rng(seed).uniform(0, 2, R)
+    return g, m, S.Sampling(mode=0, n=n), B, P, idx, meas
+
+
+def loss_of(g, m, sp, B, P, idx, meas):
+    proj, _, _, _ = O.forward(g, m, sp, B, P, idx)
+    return np.mean((meas - proj) ** 2)
+
+
+@pytest.mark.parametrize("act,out_act", [(1, 1), (1, 0), (0, 1)])
+def test_gradient_central_differences_every_parameter(act, out_act):
+    g, m, sp, B, P, idx, meas = tiny_case(act=act, out_act=out_act)
+    loss, grad, _ = O.step(g, m, sp, B, P, idx, meas)
+    assert abs(loss - loss_of(g, m, sp, B, P, idx, meas)) < 1e-14
+    fd = np.zeros_like(P)
+    for k in range(P.size):
+        hk = 1e-6 * max(1.0, abs(P[k]))
+        Pp = P.copy(); Pp[k] += hk
+        Pm = P.copy(); Pm[k] -= hk
+        fd[k] = (loss_of(g, m, sp, B, Pp, idx, meas) - loss_of(g, m, sp, B, Pm, idx, meas)) / (2 * hk)
+    scale = np.abs(grad).max()
+    err = np.abs(fd - grad)
+    # ReLU kinks can make a few FD entries meaningless; require nearly all to agree
+    ok = err <= 1e-7 * scale + 1e-9
+    assert ok.mean() >= (1.0 if act == 1 else 0.97), (err.max(), scale)
+
+
+def test_gradient_fd_on_c0_network_subset():
+    w = S.workload("c0")
+    m = dataclass_replace(w.mlp, act=1)  # Swish: smooth, so FD is meaningful
+    g = w.geom
+    B = S.make_B(m, 3).astype(np.float64)
+    P = S.make_params(m, 4).astype(np.float64)
+    idx = S.draw_rays(g, 16, 5)
+    meas = np.random.default_rng(1).uniform(0, 1.5, 16)
+    sp = S.Sampling(mode=0, n=16)
+    _, grad, _ = O.step(g, m, sp, B, P, idx, meas)
+    rng = np.random.default_rng(7)
+    n_out = m.width + 1
+    ks = np.concatenate([np.arange(P.size - n_out, P.size), rng.choice(P.size - n_out, 200, replace=False)])
+    for k in ks:
+        hk = 1e-6 * max(1.0, abs(P[k]))
+        Pp = P.copy(); Pp[k] += hk
+        Pm = P.copy(); Pm[k] -= hk
+        fd = (loss_of(g, m, sp, B, Pp, idx, meas) - loss_of(g, m, sp, B, Pm, idx, meas)) / (2 * hk)
+        assert abs(fd - grad[k]) <= 1e-7 * np.abs(grad).max() + 1e-10
+
+
+def dataclass_replace(obj, **kw):
+    import dataclasses
+    return dataclasses.replace(obj, **kw)
+
+
+def test_output_bias_gradient_closed_form():
+    """Identity output: dL/db_o = (2 mu0 / R) sum_i (pbar_i - p_i) l_i."""
+    g, m, sp, B, P, idx, meas = tiny_case(act=0, out_act=0, R=9)
+    loss, grad, proj = O.step(g, m, sp, B, P, idx, meas)
+    _, _, _, ln = O.forward(g, m, sp, B, P, idx)
+    ref = 2 * m.mu0 / len(idx) * np.sum((proj - meas) * ln)
+    assert abs(grad[-1] - ref) < 1e-13 * max(1, abs(ref))
+
+
+def test_constant_field_loss_closed_form():
+    """All weights 0, b_o = beta, identity output: M = beta everywhere, so
+    pbar_i = mu0 l_i beta and L = mean (p_i - mu0 l_i beta)^2."""
+    g, m, sp, B, P, idx, meas = tiny_case(act=0, out_act=0, R=7)
+    P = np.zeros_like(P); P[-1] = 0.37
+    loss, grad, proj = O.step(g, m, sp, B, P, idx, meas)
+    o, d, _ = S.scanner_rays(g, idx)
+    _, ln = S.scanner_fov_chord(g, o, d)
+    np.testing.assert_allclose(proj, m.mu0 * ln * 0.37, rtol=1e-14)
+    assert abs(loss - np.mean((meas - m.mu0 * ln * 0.37) ** 2)) < 1e-14
+    assert abs(grad[-1] - 2 / len(idx) * np.sum((proj - meas) * m.mu0 * ln)) < 1e-13
+
+
+def test_self_consistent_measurements_zero_loss_and_gradient():
+    g, m, sp, B, P, idx, _ = tiny_case()
+    proj, _, _, _ = O.forward(g, m, sp, B, P, idx)
+    loss, grad, _ = O.step(g, m, sp, B, P, idx, proj)
+    assert loss == 0.0 and np.all(grad == 0.0)
+
+
+def test_batch_additivity():
+    """grad L(O1 u O2) = (|O1| grad L(O1) + |O2| grad L(O2)) / |O|: the averaging
+    across processes in Sec. II is the full-batch gradient."""
+    g, m, sp, B, P, idx, meas = tiny_case(R=10)
+    _, gfull, _ = O.step(g, m, sp, B, P, idx, meas)
+    _, g1, _ = O.step(g, m, sp, B, P, idx[:4], meas[:4])
+    _, g2, _ = O.step(g, m, sp, B, P, idx[4:], meas[4:])
+    np.testing.assert_allclose(gfull, (4 * g1 + 6 * g2) / 10, rtol=1e-12, atol=1e-15)
+
+
+def test_gradient_against_torch_autograd_fp64():
+    torch = pytest.importorskip("torch")
+    g, m, sp, B, P, idx, meas = tiny_case(act=1, out_act=1, R=5, n=4)
+    _, grad, _ = O.step(g, m, sp, B, P, idx, meas)
+    # independent differentiation: torch builds the same forward from the
+    # scanner's rays and differentiates it
+    o, d, t = S.scanner_rays(g, idx)
+    s_in, ln = S.scanner_fov_chord(g, o, d)
+    n = sp.n
+    s = s_in[:, None] + (np.arange(n)[None, :] + 0.5) * (ln / n)[:, None]
+    x = o[:, None, :] + s[..., None] * d[:, None, :]
+    rb = np.stack([np.broadcast_to(2 * t[:, None] - 1, s.shape), x[..., 2], x[..., 1], x[..., 0]], -1)
+    Pt = torch.tensor(P, dtype=torch.float64, requires_grad=True)
+    h = torch.tensor(rb, dtype=torch.float64) @ torch.tensor(B, dtype=torch.float64).T
+    a = torch.cat([torch.cos(2 * math.pi * h), torch.sin(2 * math.pi * h)], -1)
+    off = 0
+    fin = 2 * m.n_freq
+    for _ in range(m.depth):
+        W = Pt[off:off + m.width * fin].view(m.width, fin); off += m.width * fin
+        b = Pt[off:off + m.width]; off += m.width
+        z = a @ W.T + b
+        a = z * torch.sigmoid(z)
+        fin = m.width
+    z = a @ Pt[off:off + m.width] + Pt[off + m.width]
+    M = torch.nn.functional.softplus(z)
+    pbar = m.mu0 * torch.tensor(ln / n) * M.sum(-1)
+    L = torch.mean((torch.tensor(meas) - pbar) ** 2)
+    L.backward()
+    np.testing.assert_allclose(grad, Pt.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal(50)
+    gr = rng.standard_normal(50)
+    p0 = p.copy()
+    mm, vv = np.zeros(50), np.zeros(50)
+    O.adam(p, gr, mm, vv, 1e-3, 0.9, 0.999, 1e-8, 1)
+    np.testing.assert_allclose(p, p0 - 1e-3 * gr / (np.abs(gr) + 1e-8), rtol=0, atol=1e-15)
