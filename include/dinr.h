@@ -1,0 +1,177 @@
+/*
+ * dinr.h -- C ABI of libdinr, the gfx950 (MI355X) implementation of one DINR
+ * training step over a sparse batch of detector rays, its forward projection
+ * and adjoint, and queries of the trained field.
+ *
+ * Method: Mohan et al., "Distributed Stochastic Optimization of a Neural
+ * Representation Network for Time-Space Tomography Reconstruction"
+ * (arXiv 2404.19075).  Section and equation numbers below are that paper's.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named *_d are device pointers (hipMalloc'd or torch-allocated
+ *    on the context's device); pointers without the suffix are host pointers.
+ *    The caller owns every buffer it passes; the library never frees them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work on that stream; outputs are valid after the
+ *    stream is synchronised.  Calls on one context must not overlap in time
+ *    (the context's workspace is shared); use one context per stream.
+ *  - Errors are negative return values; dinr_last_error() gives a message.
+ *    Argument errors are detected before anything is enqueued, and then no
+ *    output or parameter buffer is touched.  No exception crosses the ABI.
+ *  - The context allocates one device workspace of `workspace_budget` bytes
+ *    in dinr_create and nothing afterwards; a batch that cannot be processed
+ *    within it (even in chunks) is rejected with DINR_ENOMEM.
+ *  - Parameters gamma are one flat FP32 vector: for each hidden layer
+ *    l = 1..L, W_l [H x fan_in] row-major (row = output unit) then b_l [H];
+ *    then the output layer w_o [H] and b_o [1].  fan_in = 2C for l = 1 and
+ *    H otherwise.  Gradients use the same layout.
+ */
+#ifndef DINR_H
+#define DINR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DINR_OK = 0,
+  DINR_EINVAL = -1,      /* bad argument, geometry or shape */
+  DINR_ENOMEM = -2,      /* workspace budget too small, or allocation failed */
+  DINR_EHIP = -3,        /* a HIP runtime call failed */
+  DINR_ENONFINITE = -4,  /* loss or gradient norm is not finite; Adam skipped */
+  DINR_EBUSY = -5        /* serving: admission refused (budget or slots full) */
+};
+
+enum { DINR_PARALLEL = 0, DINR_CONE = 1 };
+enum { DINR_FOV_BOX = 0, DINR_FOV_CYLINDER = 1 };
+enum { DINR_RELU = 0, DINR_SWISH = 1 };
+enum { DINR_OUT_IDENTITY = 0, DINR_OUT_SOFTPLUS = 1 };
+enum { DINR_FP32 = 0, DINR_BF16 = 1 };
+
+/* Scanner geometry (Sec. II; Appendix A).  Projection index i = m N + n with
+ * N = rows*cols, view m = floor(i/N), pixel n = row*cols + col.
+ * Parallel beam: at theta = 0 rays travel along +x, detector u along +y,
+ * v along +z, pixel centre u = (col - (cols-1)/2) pitch_u + off_u,
+ * v = (row - (rows-1)/2) pitch_v + off_v.  Cone beam: point source at
+ * (-sod, 0, 0), flat detector at x = sdd - sod.  View m rotates the
+ * source-detector pair by -theta[m] about z (object rotation by theta[m]) and
+ * every sample of the view has time time[m].  The field of view is a box
+ * {x0,x1,y0,y1,z0,z1} or a z-axis cylinder {R,z0,z1}; its bounds and [t0,t1]
+ * normalise coordinates to [-1,1] (Appendix B item 1).  theta and time are
+ * host arrays of n_views entries, copied by dinr_create. */
+typedef struct {
+  int32_t kind;       /* DINR_PARALLEL or DINR_CONE */
+  int32_t rows, cols;
+  int32_t n_views;
+  int32_t fov_kind;   /* DINR_FOV_BOX or DINR_FOV_CYLINDER */
+  int32_t reserved;
+  double sod, sdd;
+  double pitch_u, pitch_v, off_u, off_v;
+  double fov[6];
+  double t0, t1;
+  const double* theta;
+  const double* time;
+} dinr_geometry;
+
+/* Coordinate network M(r; gamma) (Appendix B): normalise, Gaussian random
+ * Fourier features [cos 2 pi B r; sin 2 pi B r] (2C features), L hidden FC
+ * layers of width H with activation `act`, a linear output unit followed by
+ * `out_act`.  mu0 scales the field into attenuation units (Eq. (2)).
+ * precision: DINR_FP32 runs the MLP GEMMs on FP32 matrix cores; DINR_BF16
+ * runs them on BF16 matrix cores with FP32 accumulation.  Supported shapes:
+ * (2C, H) in {(128,64), (256,256)}, 1 <= L <= 10, act = DINR_RELU. */
+typedef struct {
+  int32_t n_freq;     /* C */
+  int32_t width;      /* H */
+  int32_t depth;      /* L */
+  int32_t act;
+  int32_t out_act;
+  int32_t precision;
+  int32_t reserved0, reserved1;
+  double mu0;
+} dinr_mlp;
+
+/* Samples per ray (Appendix A): equi-spaced midpoints of n equal segments of
+ * the ray's chord inside the FOV.  mode 0: n fixed; mode 1: n = clamp(ceil(l/h),
+ * n_min, n_max) with l the chord length.  A ray missing the FOV has n = 0 and
+ * predicted projection 0. */
+typedef struct {
+  int32_t mode;
+  int32_t n;
+  int32_t n_min, n_max;
+  double h;
+} dinr_sampling;
+
+/* Adam state for dinr_step (Sec. II, Appendix C).  m_d, v_d: device FP32
+ * [n_params], caller-owned, updated in place.  `step` is the 1-based index of
+ * this update (bias correction uses beta^step). */
+typedef struct {
+  float* m_d;
+  float* v_d;
+  float lr, beta1, beta2, eps;
+  int64_t step;
+} dinr_adam;
+
+typedef struct dinr_ctx dinr_ctx;
+
+/* Create a context on the current HIP device.  B_host: frozen GRFF matrix,
+ * host FP32 [C][4], columns ordered (t, z, y, x) (Appendix B item 2).
+ * workspace_budget: bytes of device memory the context may hold.
+ * Returns DINR_EINVAL for an unsupported or inconsistent description,
+ * DINR_ENOMEM if the budget is below the minimum (a few MB) or cannot be
+ * allocated. */
+int dinr_create(const dinr_geometry* geom, const dinr_mlp* mlp, const dinr_sampling* samp,
+                const float* B_host, size_t workspace_budget, dinr_ctx** out);
+
+int dinr_destroy(dinr_ctx* ctx);
+
+/* Message of the last error on this context (static storage of the context). */
+const char* dinr_last_error(const dinr_ctx* ctx);
+
+/* Number of parameters of the context's network. */
+int64_t dinr_num_params(const dinr_ctx* ctx);
+
+/* Forward projection, Eq. (1)/(7): for each ray r of the batch,
+ * proj_out_d[r] = (1/n_r) sum_j mu0 l_r M(r_{r,j}; gamma).
+ * params_d: device FP32 [n_params].  proj_idx_d: device int64 [R], each in
+ * [0, n_views*rows*cols) (checked on the device: an out-of-range index yields
+ * n = 0 and projection NaN).  proj_out_d: device FP32 [R].  n_out_d: device
+ * int32 [R] receiving the sample count of each ray, or NULL. */
+int dinr_forward_project(dinr_ctx* ctx, const float* params_d, const int64_t* proj_idx_d,
+                         int64_t R, float* proj_out_d, int32_t* n_out_d, void* stream);
+
+/* Adjoint of dinr_forward_project: given dL/dpbar_r in dproj_d (device FP32
+ * [R]), writes dL/dgamma = sum_r dproj_r dpbar_r/dgamma (Eq. (8) with an
+ * arbitrary upstream) to grad_out_d (device FP32 [n_params], overwritten).
+ * gnorm_d (nullable): device double receiving ||grad||^2 computed in FP64. */
+int dinr_project_backward(dinr_ctx* ctx, const float* params_d, const int64_t* proj_idx_d,
+                          int64_t R, const float* dproj_d, float* grad_out_d, double* gnorm_d,
+                          void* stream);
+
+/* One training step on the batch (Eqs. (1), (3), (5), (8)):
+ * pbar = forward projection, loss = (1/R) sum_r (meas_r - pbar_r)^2 reduced in
+ * FP64, grad = dloss/dgamma (hand-written adjoint; weight gradients summed
+ * with FP32 compensated summation), gnorm = ||grad||^2 in FP64.
+ * meas_d: device FP32 [R].  proj_out_d (nullable): device FP32 [R].
+ * grad_out_d: device FP32 [n_params], overwritten.  loss_d, gnorm_d: device
+ * double (nullable).  adam (nullable): when given, params_d is updated in
+ * place by one Adam step with the new gradient -- unless the loss or the
+ * gradient norm is not finite, which the device checks before updating (the
+ * parameters are then left unchanged); dinr_step_status reports it. */
+int dinr_step(dinr_ctx* ctx, float* params_d, const int64_t* proj_idx_d, int64_t R,
+              const float* meas_d, float* proj_out_d, float* grad_out_d, double* loss_d,
+              double* gnorm_d, const dinr_adam* adam, void* stream);
+
+/* Synchronises `stream` and returns DINR_ENONFINITE if the last dinr_step on
+ * this context produced a non-finite loss or gradient norm (Adam, if
+ * requested, was then skipped), else DINR_OK. */
+int dinr_step_status(dinr_ctx* ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DINR_H */

@@ -1,0 +1,556 @@
+// dinr_api.hip -- the C ABI of include/dinr.h: context, validation, the
+// workspace arena and the launch sequences of forward projection, adjoint and
+// training step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dinr.h"
+#include "kernels.h"
+
+using namespace dinr;
+
+struct dinr_ctx {
+  int device = 0;
+  int n_cu = 0;
+  dinr_geometry geom{};
+  dinr_mlp mlp{};
+  dinr_sampling samp{};
+  int IN = 0, H = 0, L = 0, prec = 0, tile = 0, nmax = 0;
+  int64_t np = 0, nh = 0;
+  std::vector<int64_t> w_off, b_off;
+  int64_t wo_off = 0, bo_off = 0;
+  // device tables
+  float* d_cth = nullptr;
+  float* d_sth = nullptr;
+  float* d_tn = nullptr;
+  float4* d_B = nullptr;
+  // workspace arena
+  char* arena = nullptr;
+  size_t arena_size = 0;
+  int32_t* d_status = nullptr;  // [0] Adam skipped (non-finite)
+  double* d_scal = nullptr;     // [0] loss, [1] gnorm
+  char err[512] = {0};
+  GeomDev gd{};
+};
+
+static int fail(dinr_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, x)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess)                                                           \
+      return fail(ctx, DINR_EHIP, "%s failed: %s", #x, hipGetErrorString(e_));       \
+  } while (0)
+
+namespace {
+
+struct Arena {
+  char* base;
+  size_t cap, used = 0;
+  bool ok = true;
+  template <class T>
+  T* take(size_t n) {
+    size_t off = (used + 255) & ~(size_t)255;
+    size_t bytes = n * sizeof(T);
+    if (off + bytes > cap) {
+      ok = false;
+      return nullptr;
+    }
+    used = off + bytes;
+    return (T*)(base + off);
+  }
+};
+
+// Everything one call needs, carved from the arena.
+struct Plan {
+  int64_t R = 0, n_tiles_max = 0, points_max = 0;
+  RayRec* rays = nullptr;
+  int32_t* nray = nullptr;
+  int64_t* off = nullptr;
+  int32_t* tr0 = nullptr;
+  float* part = nullptr;
+  float* gup = nullptr;
+  float* proj = nullptr;
+  void* Wpk = nullptr;
+  void* WTpk = nullptr;
+  float* bias = nullptr;
+  float* wo = nullptr;
+  PackArgs pk{};
+  // adjoint
+  void* stash = nullptr;
+  int64_t chunk_points = 0, n_chunks = 0, kb = 0, splits_per_chunk = 0;
+  int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS];
+  float* wpart = nullptr;
+  float* opart = nullptr;
+  double* gn_part = nullptr;
+  int grid_mlp = 0;
+};
+
+size_t esize(int prec) { return prec == DINR_BF16 ? 2 : 4; }
+
+bool shape_supported(int in, int h) { return (in == 128 && h == 64) || (in == 256 && h == 256); }
+
+}  // namespace
+
+static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
+  Arena A{c->arena, c->arena_size};
+  // status and scalars live at the start of the arena
+  c->d_status = A.take<int32_t>(4);
+  c->d_scal = A.take<double>(4);
+  p->R = R;
+  p->points_max = R * (int64_t)c->nmax;
+  p->n_tiles_max = (p->points_max + c->tile - 1) / c->tile;
+  p->rays = A.take<RayRec>(std::max<int64_t>(R, 1));
+  p->nray = A.take<int32_t>(std::max<int64_t>(R, 1));
+  p->off = A.take<int64_t>(R + 1);
+  p->tr0 = A.take<int32_t>(p->n_tiles_max + 1);
+  p->part = A.take<float>(2 * std::max<int64_t>(p->n_tiles_max, 1));
+  p->gup = A.take<float>(std::max<int64_t>(R, 1));
+  p->proj = A.take<float>(std::max<int64_t>(R, 1));
+  // packed weights
+  const int vpc = c->prec == DINR_BF16 ? 8 : 4;
+  (void)vpc;
+  PackArgs& k = p->pk;
+  k.L = c->L;
+  k.IN = c->IN;
+  k.H = c->H;
+  int64_t o = 0;
+  for (int l = 0; l < c->L; ++l) {
+    k.pk_off[l] = o;
+    o += (int64_t)c->H * (l == 0 ? c->IN : c->H);
+    k.w_off[l] = c->w_off[l];
+    k.b_off[l] = c->b_off[l];
+  }
+  k.n_w = o;
+  o = 0;
+  for (int l = 0; l < c->L; ++l) {
+    k.pkT_off[l] = o;
+    if (l >= 1) o += (int64_t)c->H * c->H;
+  }
+  k.n_wt = o;
+  k.wo_off = c->wo_off;
+  p->Wpk = A.take<char>(k.n_w * esize(c->prec));
+  p->WTpk = A.take<char>(std::max<int64_t>(k.n_wt, 1) * esize(c->prec));
+  p->bias = A.take<float>((size_t)c->L * c->H);
+  p->wo = A.take<float>(c->H);
+  p->grid_mlp = c->n_cu;
+  if (!A.ok) return fail(c, DINR_ENOMEM, "workspace budget too small for R=%lld", (long long)R);
+  if (!adjoint) return DINR_OK;
+
+  // adjoint: split partials for the whole batch, output-layer partials per
+  // chunk, then as large a stash chunk as the remaining budget allows.
+  const int64_t k_split = 16384;  // points summed by one weight-gradient workgroup
+  p->kb = k_split / 32;
+  int64_t per_point = 0;  // stash elements per point
+  for (int l = 0; l < c->L; ++l) per_point += (l == 0 ? c->IN : c->H) + c->H;
+  const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
+  const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
+  const int64_t total_splits = pts_pad / k_split;
+  p->wpart = A.take<float>((size_t)total_splits * c->nh);
+  p->gn_part = A.take<double>((size_t)((c->np + 255) / 256));
+  if (!A.ok) return fail(c, DINR_ENOMEM, "workspace budget too small for the gradient partials");
+  // try the whole batch in one chunk, then halve
+  int64_t chunk = pts_pad;
+  const size_t used0 = A.used;
+  for (;;) {
+    A.used = used0;
+    A.ok = true;
+    const int64_t n_chunks = (pts_pad + chunk - 1) / chunk;
+    p->opart = A.take<float>((size_t)n_chunks * p->grid_mlp * (c->H + 1));
+    p->stash = A.take<char>((size_t)chunk * per_point * esize(c->prec));
+    if (A.ok) {
+      p->chunk_points = chunk;
+      p->n_chunks = n_chunks;
+      break;
+    }
+    if (chunk <= quantum)
+      return fail(c, DINR_ENOMEM, "workspace budget too small for a stash of %lld points",
+                  (long long)chunk);
+    chunk = std::max<int64_t>(quantum, (chunk / 2 + quantum - 1) / quantum * quantum);
+  }
+  p->splits_per_chunk = p->chunk_points / k_split;
+  // stash region of each layer: h blocks then delta blocks, in 16-byte chunks
+  int64_t base = 0;
+  const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
+  for (int l = 0; l < c->L; ++l) {
+    const int fin = (l == 0) ? c->IN : c->H;
+    p->h_base[l] = base;
+    base += (p->chunk_points / 32) * (fin / vpc2) * 64;
+    p->d_base[l] = base;
+    base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
+  }
+  return DINR_OK;
+}
+
+static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
+  MlpArgs a{};
+  a.rays = p.rays;
+  a.off = p.off;
+  a.tile_ray0 = p.tr0;
+  a.R = p.R;
+  a.Bmat = c->d_B;
+  a.params = params;
+  a.bo_off = c->bo_off;
+  a.Wpk = p.Wpk;
+  a.WTpk = p.WTpk;
+  a.bias = p.bias;
+  a.wo_perm = p.wo;
+  for (int l = 0; l < c->L; ++l) {
+    a.wpk_off[l] = p.pk.pk_off[l];
+    a.wtpk_off[l] = p.pk.pkT_off[l];
+  }
+  a.L = c->L;
+  a.out_act = c->mlp.out_act;
+  a.tile_begin = 0;
+  a.tile_end = p.n_tiles_max;
+  a.part = p.part;
+  a.proj = nullptr;
+  return a;
+}
+
+static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
+                           const int64_t* idx, float* proj, int32_t* n_out, hipStream_t st) {
+  HIPCHK(c, launch_rays(c->gd, idx, p.R, p.rays, p.nray, n_out, p.off, c->tile, p.n_tiles_max,
+                        p.tr0, st));
+  HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
+                        p.bias, p.wo, st));
+  MlpArgs a = mlp_args(c, p, params);
+  a.proj = proj;
+  HIPCHK(c, launch_mlp(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, c->IN, c->H, MODE_FWD, a,
+                       p.grid_mlp, st));
+  HIPCHK(c, launch_fixup(p.rays, p.off, p.R, c->tile, p.part, proj, st));
+  return DINR_OK;
+}
+
+// Adjoint given the upstream gradient in gup (rays, offsets and packed
+// weights already in place).
+static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, const float* gup,
+                           float* grad, double* gnorm_out, hipStream_t st) {
+  const int prec = c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32;
+  const int64_t tiles_per_chunk = p.chunk_points / c->tile;
+  for (int64_t ch = 0; ch < p.n_chunks; ++ch) {
+    MlpArgs a = mlp_args(c, p, params);
+    a.tile_begin = ch * tiles_per_chunk;
+    a.tile_end = std::min<int64_t>((ch + 1) * tiles_per_chunk, p.n_tiles_max);
+    a.gup = gup;
+    a.stash = p.stash;
+    for (int l = 0; l < c->L; ++l) {
+      a.h_base[l] = p.h_base[l];
+      a.d_base[l] = p.d_base[l];
+    }
+    a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
+    HIPCHK(c, launch_mlp(prec, c->IN, c->H, MODE_BWD, a, p.grid_mlp, st));
+    for (int l = 0; l < c->L; ++l) {
+      WgArgs w{};
+      w.off = p.off;
+      w.R = p.R;
+      w.tile = c->tile;
+      w.chunk_p0 = ch * p.chunk_points;
+      w.chunk_p1 = (ch + 1) * p.chunk_points;
+      w.kb = p.kb;
+      w.stash = p.stash;
+      w.d_base = p.d_base[l];
+      w.h_base = p.h_base[l];
+      w.wpart = p.wpart;
+      w.split_base = ch * p.splits_per_chunk;
+      w.nh = c->nh;
+      w.w_off = c->w_off[l];
+      w.b_off = c->b_off[l];
+      w.layer = l;
+      HIPCHK(c, launch_wgrad(prec, l == 0 ? c->IN : c->H, c->H, w, (int)p.splits_per_chunk, st));
+    }
+  }
+  RedArgs r{};
+  r.off = p.off;
+  r.R = p.R;
+  r.tile = c->tile;
+  r.n_chunks = p.n_chunks;
+  r.chunk_points = p.chunk_points;
+  r.kb = p.kb;
+  r.splits_per_chunk = p.splits_per_chunk;
+  r.wpart = p.wpart;
+  r.nh = c->nh;
+  r.opart = p.opart;
+  r.n_opart = p.n_chunks * p.grid_mlp;
+  r.no = c->H + 1;
+  r.np = c->np;
+  r.grad = grad;
+  r.gn_part = p.gn_part;
+  HIPCHK(c, launch_reduce(r, c->d_scal + 1, gnorm_out, st));
+  return DINR_OK;
+}
+
+extern "C" {
+
+int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* s,
+                const float* B_host, size_t budget, dinr_ctx** out) {
+  if (!out) return DINR_EINVAL;
+  *out = nullptr;
+  if (!g || !m || !s || !B_host) return DINR_EINVAL;
+  dinr_ctx* c = new (std::nothrow) dinr_ctx();
+  if (!c) return DINR_ENOMEM;
+  auto bad = [&](const char* msg) {
+    fail(c, DINR_EINVAL, "%s", msg);
+    return DINR_EINVAL;
+  };
+  int rc = DINR_OK;
+  do {
+    if (g->kind != DINR_PARALLEL && g->kind != DINR_CONE) { rc = bad("geometry kind"); break; }
+    if (g->rows <= 0 || g->cols <= 0 || g->n_views <= 0) { rc = bad("detector shape"); break; }
+    if (!g->theta || !g->time) { rc = bad("theta/time tables"); break; }
+    if (g->kind == DINR_CONE && !(g->sdd > 0 && g->sod > 0 && g->sdd > g->sod)) {
+      rc = bad("cone geometry needs 0 < sod < sdd");
+      break;
+    }
+    if (!(g->pitch_u > 0 && g->pitch_v > 0)) { rc = bad("pixel pitch"); break; }
+    if (g->fov_kind == DINR_FOV_BOX) {
+      if (!(g->fov[1] > g->fov[0] && g->fov[3] > g->fov[2] && g->fov[5] > g->fov[4])) {
+        rc = bad("box FOV bounds");
+        break;
+      }
+    } else if (g->fov_kind == DINR_FOV_CYLINDER) {
+      if (!(g->fov[0] > 0 && g->fov[2] > g->fov[1])) { rc = bad("cylinder FOV"); break; }
+    } else {
+      rc = bad("fov_kind");
+      break;
+    }
+    if (!(g->t1 > g->t0)) { rc = bad("time range"); break; }
+    const int IN = 2 * m->n_freq, H = m->width;
+    if (!shape_supported(IN, H)) { rc = bad("unsupported (2C, H): supported (128,64), (256,256)"); break; }
+    if (m->depth < 1 || m->depth > MAX_LAYERS) { rc = bad("depth must be in [1, 10]"); break; }
+    if (m->act != DINR_RELU) { rc = bad("only ReLU hidden activations are implemented"); break; }
+    if (m->out_act != DINR_OUT_IDENTITY && m->out_act != DINR_OUT_SOFTPLUS) { rc = bad("out_act"); break; }
+    if (m->precision != DINR_FP32 && m->precision != DINR_BF16) { rc = bad("precision"); break; }
+    if (!std::isfinite(m->mu0)) { rc = bad("mu0"); break; }
+    if (s->mode == 0) {
+      if (s->n < 1 || s->n > (1 << 20)) { rc = bad("samples per ray"); break; }
+    } else if (s->mode == 1) {
+      if (!(s->h > 0) || s->n_min < 1 || s->n_max < s->n_min || s->n_max > (1 << 20)) {
+        rc = bad("step sampling");
+        break;
+      }
+    } else {
+      rc = bad("sampling mode");
+      break;
+    }
+    for (int k = 0; k < 4 * m->n_freq; ++k)
+      if (!std::isfinite(B_host[k])) { rc = bad("B has a non-finite entry"); break; }
+    if (rc) break;
+    for (int v = 0; v < g->n_views; ++v)
+      if (!std::isfinite(g->theta[v]) || !std::isfinite(g->time[v])) { rc = bad("theta/time"); break; }
+    if (rc) break;
+    if (budget < ((size_t)8 << 20)) {
+      rc = fail(c, DINR_ENOMEM, "workspace budget below 8 MiB");
+      break;
+    }
+  } while (0);
+  if (rc) {
+    // keep the message reachable: a context that failed creation is returned
+    // only through the error code, so print nothing and free it
+    delete c;
+    return rc;
+  }
+  c->geom = *g;
+  c->geom.theta = nullptr;
+  c->geom.time = nullptr;
+  c->mlp = *m;
+  c->samp = *s;
+  c->IN = 2 * m->n_freq;
+  c->H = m->width;
+  c->L = m->depth;
+  c->prec = m->precision;
+  c->tile = WAVES_PER_WG * 32 * (m->precision == DINR_BF16 ? 2 : 1);
+  c->nmax = s->mode == 0 ? s->n : s->n_max;
+  int64_t o = 0;
+  for (int l = 0; l < c->L; ++l) {
+    const int fin = l == 0 ? c->IN : c->H;
+    c->w_off.push_back(o);
+    o += (int64_t)c->H * fin;
+    c->b_off.push_back(o);
+    o += c->H;
+  }
+  c->nh = o;
+  c->wo_off = o;
+  c->bo_off = o + c->H;
+  c->np = o + c->H + 1;
+
+  hipError_t e = hipGetDevice(&c->device);
+  hipDeviceProp_t prop;
+  if (e == hipSuccess) e = hipGetDeviceProperties(&prop, c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return DINR_EHIP;
+  }
+  c->n_cu = prop.multiProcessorCount;
+  const int nv = g->n_views;
+  std::vector<float> cth(nv), sth(nv), tn(nv);
+  for (int v = 0; v < nv; ++v) {
+    cth[v] = (float)std::cos(g->theta[v]);
+    sth[v] = (float)std::sin(g->theta[v]);
+    tn[v] = (float)(2.0 * (g->time[v] - g->t0) / (g->t1 - g->t0) - 1.0);
+  }
+  std::vector<float> Bv(4 * m->n_freq);
+  std::memcpy(Bv.data(), B_host, sizeof(float) * Bv.size());
+  if (hipMalloc(&c->d_cth, nv * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->d_sth, nv * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->d_tn, nv * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->d_B, Bv.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&c->arena, budget) != hipSuccess) {
+    dinr_destroy(c);
+    return DINR_ENOMEM;
+  }
+  c->arena_size = budget;
+  if (hipMemcpy(c->d_cth, cth.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_sth, sth.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_tn, tn.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_B, Bv.data(), Bv.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    dinr_destroy(c);
+    return DINR_EHIP;
+  }
+  GeomDev& d = c->gd;
+  d.kind = g->kind;
+  d.rows = g->rows;
+  d.cols = g->cols;
+  d.n_views = g->n_views;
+  d.fov_kind = g->fov_kind;
+  d.samp_mode = s->mode;
+  d.samp_n = s->n;
+  d.samp_min = s->n_min;
+  d.samp_max = s->n_max;
+  d.samp_h = (float)s->h;
+  d.sod = (float)g->sod;
+  d.sdd = (float)g->sdd;
+  d.pitch_u = (float)g->pitch_u;
+  d.pitch_v = (float)g->pitch_v;
+  d.off_u = (float)g->off_u;
+  d.off_v = (float)g->off_v;
+  for (int k = 0; k < 6; ++k) d.fov[k] = (float)g->fov[k];
+  double lo[3], hi[3];
+  if (g->fov_kind == DINR_FOV_BOX) {
+    for (int a = 0; a < 3; ++a) { lo[a] = g->fov[2 * a]; hi[a] = g->fov[2 * a + 1]; }
+  } else {
+    lo[0] = lo[1] = -g->fov[0];
+    hi[0] = hi[1] = g->fov[0];
+    lo[2] = g->fov[1];
+    hi[2] = g->fov[2];
+  }
+  for (int a = 0; a < 3; ++a) {
+    d.sc[a] = (float)(2.0 / (hi[a] - lo[a]));
+    d.oc[a] = (float)(-2.0 * lo[a] / (hi[a] - lo[a]) - 1.0);
+  }
+  d.mu0 = (float)m->mu0;
+  d.cth = c->d_cth;
+  d.sth = c->d_sth;
+  d.tnorm = c->d_tn;
+  *out = c;
+  return DINR_OK;
+}
+
+int dinr_destroy(dinr_ctx* c) {
+  if (!c) return DINR_OK;
+  hipFree(c->d_cth);
+  hipFree(c->d_sth);
+  hipFree(c->d_tn);
+  hipFree(c->d_B);
+  hipFree(c->arena);
+  delete c;
+  return DINR_OK;
+}
+
+const char* dinr_last_error(const dinr_ctx* c) { return c ? c->err : "null context"; }
+
+int64_t dinr_num_params(const dinr_ctx* c) { return c ? c->np : -1; }
+
+int dinr_forward_project(dinr_ctx* c, const float* params, const int64_t* idx, int64_t R,
+                         float* proj, int32_t* n_out, void* stream) {
+  if (!c) return DINR_EINVAL;
+  if (R < 0 || R > (int64_t)INT32_MAX - 1) return fail(c, DINR_EINVAL, "R out of range");
+  if (R > 0 && (!params || !idx || !proj)) return fail(c, DINR_EINVAL, "null buffer");
+  if (R == 0) return DINR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  Plan p;
+  int rc = plan_call(c, R, false, &p);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  return enqueue_forward(c, p, params, idx, proj, n_out, st);
+}
+
+int dinr_project_backward(dinr_ctx* c, const float* params, const int64_t* idx, int64_t R,
+                          const float* dproj, float* grad, double* gnorm, void* stream) {
+  if (!c) return DINR_EINVAL;
+  if (R < 0 || R > (int64_t)INT32_MAX - 1) return fail(c, DINR_EINVAL, "R out of range");
+  if (!params || !grad || (R > 0 && (!idx || !dproj))) return fail(c, DINR_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  Plan p;
+  int rc = plan_call(c, R, true, &p);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
+                        p.tr0, st));
+  HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
+                        p.bias, p.wo, st));
+  return enqueue_adjoint(c, p, params, dproj, grad, gnorm, st);
+}
+
+int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const float* meas,
+              float* proj_out, float* grad, double* loss, double* gnorm, const dinr_adam* adam,
+              void* stream) {
+  if (!c) return DINR_EINVAL;
+  if (R < 1 || R > (int64_t)INT32_MAX - 1) return fail(c, DINR_EINVAL, "R out of range");
+  if (!params || !idx || !meas || !grad) return fail(c, DINR_EINVAL, "null buffer");
+  if (adam) {
+    if (!adam->m_d || !adam->v_d) return fail(c, DINR_EINVAL, "Adam state buffers");
+    if (adam->step < 1) return fail(c, DINR_EINVAL, "Adam step must be >= 1");
+    if (!(adam->lr > 0) || !(adam->beta1 >= 0 && adam->beta1 < 1) ||
+        !(adam->beta2 >= 0 && adam->beta2 < 1) || !(adam->eps > 0))
+      return fail(c, DINR_EINVAL, "Adam hyper-parameters");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  Plan p;
+  int rc = plan_call(c, R, true, &p);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  float* proj = proj_out ? proj_out : p.proj;
+  rc = enqueue_forward(c, p, params, idx, proj, nullptr, st);
+  if (rc) return rc;
+  HIPCHK(c, launch_loss(proj, meas, R, p.gup, c->d_scal, st));
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
+  rc = enqueue_adjoint(c, p, params, p.gup, grad, gnorm, st);
+  if (rc) return rc;
+  if (adam) {
+    const float c1 = (float)(1.0 - std::pow((double)adam->beta1, (double)adam->step));
+    const float c2 = (float)(1.0 - std::pow((double)adam->beta2, (double)adam->step));
+    HIPCHK(c, launch_adam(params, grad, adam->m_d, adam->v_d, c->np, adam->lr, adam->beta1,
+                          adam->beta2, adam->eps, c1, c2, c->d_scal, c->d_scal + 1, c->d_status,
+                          st));
+  }
+  return DINR_OK;
+}
+
+int dinr_step_status(dinr_ctx* c, void* stream) {
+  if (!c) return DINR_EINVAL;
+  double sc[2] = {0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(sc, c->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           (hipStream_t)stream));
+  HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+  if (!std::isfinite(sc[0]) || !std::isfinite(sc[1]))
+    return fail(c, DINR_ENONFINITE, "loss or gradient norm not finite; Adam step skipped");
+  return DINR_OK;
+}
+
+}  // extern "C"

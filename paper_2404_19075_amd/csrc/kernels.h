@@ -1,0 +1,110 @@
+// kernels.h -- argument blocks and launchers of the libdinr kernels
+// (internal to the library; the public interface is include/dinr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dinr_dev.h"
+
+namespace dinr {
+
+constexpr int MAX_LAYERS = 10;
+enum { MODE_FWD = 0, MODE_BWD = 1 };
+
+struct GeomDev {
+  int kind, rows, cols, n_views, fov_kind;
+  int samp_mode, samp_n, samp_min, samp_max;
+  float samp_h;
+  float sod, sdd, pitch_u, pitch_v, off_u, off_v;
+  float fov[6];
+  float sc[3], oc[3];  // x_norm = x * sc + oc per axis (x, y, z)
+  float mu0;
+  const float* cth;    // [n_views] cos(theta_m)
+  const float* sth;    // [n_views] sin(theta_m)
+  const float* tnorm;  // [n_views] normalised time of view m
+};
+
+struct PackArgs {
+  int L, IN, H;
+  int64_t n_w, n_wt;                // packed elements, forward / transposed
+  int64_t pk_off[MAX_LAYERS];       // element offset of layer l in the forward pack
+  int64_t pkT_off[MAX_LAYERS];      // element offset of layer l (l >= 1) in the transposed pack
+  int64_t w_off[MAX_LAYERS];        // offset of W_l in the flat parameters
+  int64_t b_off[MAX_LAYERS];        // offset of b_l in the flat parameters
+  int64_t wo_off;                   // offset of w_o
+};
+
+struct MlpArgs {
+  const RayRec* rays;
+  const int64_t* off;        // [R+1] point offsets
+  const int32_t* tile_ray0;  // [n_tiles+1]
+  int64_t R;
+  const float4* Bmat;        // [C] GRFF rows (t, z, y, x)
+  const float* params;       // flat FP32 parameters (for b_o)
+  int64_t bo_off;
+  const void* Wpk;
+  const void* WTpk;
+  const float* bias;         // [L][H]
+  const float* wo_perm;      // [2][H/2] w_o in register-slot order
+  int64_t wpk_off[MAX_LAYERS];
+  int64_t wtpk_off[MAX_LAYERS];
+  int L, out_act;
+  int64_t tile_begin, tile_end;
+  // forward outputs
+  float* part;               // [2 n_tiles] partial ray-sums
+  float* proj;               // [R]
+  // adjoint inputs/outputs
+  const float* gup;          // [R] dL/dpbar
+  void* stash;
+  int64_t h_base[MAX_LAYERS];  // chunk (16 B) offsets of h_l blocks
+  int64_t d_base[MAX_LAYERS];  // chunk offsets of delta_l blocks
+  float* opart;              // [grid][H+1] output-layer gradient partials
+};
+
+struct WgArgs {
+  const int64_t* off;
+  int64_t R;
+  int tile;
+  int64_t chunk_p0, chunk_p1;  // point range of this stash chunk
+  int64_t kb;                  // 32-point blocks per split
+  const void* stash;
+  int64_t d_base, h_base;      // chunk offsets of this layer's delta / h blocks
+  float* wpart;                // [splits][nh]
+  int64_t split_base, nh;
+  int64_t w_off, b_off;
+  int layer;
+};
+
+struct RedArgs {
+  const int64_t* off;
+  int64_t R;
+  int tile;
+  int64_t n_chunks, chunk_points, kb, splits_per_chunk;
+  const float* wpart;
+  int64_t nh;
+  const float* opart;
+  int64_t n_opart, no;
+  int64_t np;
+  float* grad;
+  double* gn_part;
+};
+
+hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* rays, int32_t* nray,
+                       int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
+                       hipStream_t st);
+hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, void* WTpk,
+                       float* bias, float* wo, hipStream_t st);
+hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int grid,
+                      hipStream_t st);
+hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int tile,
+                        const float* part, float* proj, hipStream_t st);
+hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
+                       hipStream_t st);
+hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st);
+hipError_t launch_reduce(const RedArgs& a, double* gnorm_ws, double* gnorm_out, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, const double* loss,
+                       const double* gnorm, int32_t* status, hipStream_t st);
+
+}  // namespace dinr

@@ -1,0 +1,923 @@
+// kernels.hip -- gfx950 kernels of one DINR training step.
+//
+//   k_rays       per ray: index -> view/pixel -> ray, FOV clip, sample count
+//   k_scan       exclusive scan of sample counts -> ragged point offsets
+//   k_tiles      first ray of every point tile
+//   k_pack       FP32 parameters -> matrix-core operand fragments (W and W^T)
+//   k_mlp        per point tile: coordinates, Fourier features, the MLP on
+//                matrix cores with activations resident in registers; then
+//                either the segmented ray-sum (forward) or the adjoint chain
+//                with operand stashes for the weight gradient (backward)
+//   k_fixup      ray-sums of rays that cross tile boundaries (compensated)
+//   k_loss       residuals, FP64 loss, upstream gradient 2(pbar-p)/R
+//   k_wgrad      dW = sum_p delta_p h_p^T over the stash, split over points
+//   k_reduce     compensated sum of the split partials, FP64 ||g||^2
+//   k_adam       Adam update guarded by a finiteness check
+#include "dinr_dev.h"
+#include "kernels.h"
+
+namespace dinr {
+
+// ------------------------------------------------------------------ rays
+//
+// Ray of projection index i (Sec. II): m = i / N, n = i mod N.  The ray is
+// parametrised from its point closest to the origin (for the cone beam
+// p0 = d x (o x d), which has no cancellation), so sample positions stay O(1)
+// in FP32.  Object rotation by theta equals rotating the source-detector pair
+// by -theta about z.  Coordinates are stored already normalised to [-1,1]
+// (Appendix B item 1).
+__global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
+                       RayRec* __restrict__ rays, int32_t* __restrict__ nray,
+                       int32_t* __restrict__ n_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  RayRec rec;
+  const int64_t i = idx[r];
+  const int64_t N = (int64_t)g.rows * g.cols;
+  if (i < 0 || i >= N * g.n_views) {
+    rec.px = rec.py = rec.pz = rec.s_in = 0.f;
+    rec.dx = rec.dy = rec.dz = rec.dl = 0.f;
+    rec.tn = 0.f;
+    rec.wgt = 0.f;
+    rec.n = 0;
+    rec.flags = 1;
+    rays[r] = rec;
+    nray[r] = 0;
+    if (n_out) n_out[r] = 0;
+    return;
+  }
+  const int m = (int)(i / N);
+  const int64_t pix = i - (int64_t)m * N;
+  const int row = (int)(pix / g.cols);
+  const int col = (int)(pix - (int64_t)row * g.cols);
+  const float u = ((float)col - 0.5f * (float)(g.cols - 1)) * g.pitch_u + g.off_u;
+  const float v = ((float)row - 0.5f * (float)(g.rows - 1)) * g.pitch_v + g.off_v;
+  float p0x, p0y, p0z, d0x, d0y, d0z;
+  if (g.kind == 0) {
+    p0x = 0.f; p0y = u; p0z = v;
+    d0x = 1.f; d0y = 0.f; d0z = 0.f;
+  } else {
+    const float nrm = sqrtf(g.sdd * g.sdd + u * u + v * v);
+    d0x = g.sdd / nrm; d0y = u / nrm; d0z = v / nrm;
+    p0x = -g.sod * (d0y * d0y + d0z * d0z);
+    p0y = g.sod * d0x * d0y;
+    p0z = g.sod * d0x * d0z;
+  }
+  const float c = g.cth[m], s = g.sth[m];
+  const float px = c * p0x + s * p0y, py = -s * p0x + c * p0y, pz = p0z;
+  const float dx = c * d0x + s * d0y, dy = -s * d0x + c * d0y, dz = d0z;
+  // FOV clip
+  float lo = -INFINITY, hi = INFINITY;
+  bool miss = false;
+  if (g.fov_kind == 0) {
+    const float o[3] = {px, py, pz}, d[3] = {dx, dy, dz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float b0 = g.fov[2 * a], b1 = g.fov[2 * a + 1];
+      if (d[a] == 0.f) {
+        if (o[a] < b0 || o[a] > b1) miss = true;
+      } else {
+        float ta = (b0 - o[a]) / d[a], tb = (b1 - o[a]) / d[a];
+        lo = fmaxf(lo, fminf(ta, tb));
+        hi = fminf(hi, fmaxf(ta, tb));
+      }
+    }
+  } else {
+    const float Rc = g.fov[0], z0 = g.fov[1], z1 = g.fov[2];
+    const float qa = dx * dx + dy * dy;
+    const float qb = px * dx + py * dy;  // half of the linear coefficient
+    const float qc = px * px + py * py - Rc * Rc;
+    if (qa == 0.f) {
+      if (qc > 0.f) miss = true;
+    } else {
+      const float disc = qb * qb - qa * qc;
+      if (disc <= 0.f) {
+        miss = true;
+      } else {
+        const float sq = sqrtf(disc);
+        lo = (-qb - sq) / qa;
+        hi = (-qb + sq) / qa;
+      }
+    }
+    if (dz == 0.f) {
+      if (pz < z0 || pz > z1) miss = true;
+    } else {
+      float ta = (z0 - pz) / dz, tb = (z1 - pz) / dz;
+      lo = fmaxf(lo, fminf(ta, tb));
+      hi = fminf(hi, fmaxf(ta, tb));
+    }
+  }
+  float len = (!miss && hi > lo) ? hi - lo : 0.f;
+  int n = 0;
+  if (len > 0.f) {
+    if (g.samp_mode == 0) {
+      n = g.samp_n;
+    } else {
+      float q = ceilf(len / g.samp_h);
+      q = fminf(fmaxf(q, (float)g.samp_min), (float)g.samp_max);
+      n = (int)q;
+    }
+  }
+  rec.px = px * g.sc[0] + g.oc[0];
+  rec.py = py * g.sc[1] + g.oc[1];
+  rec.pz = pz * g.sc[2] + g.oc[2];
+  rec.dx = dx * g.sc[0];
+  rec.dy = dy * g.sc[1];
+  rec.dz = dz * g.sc[2];
+  rec.s_in = (n > 0) ? lo : 0.f;
+  rec.dl = (n > 0) ? len / (float)n : 0.f;
+  rec.tn = g.tnorm[m];
+  rec.wgt = (n > 0) ? g.mu0 * len / (float)n : 0.f;
+  rec.n = n;
+  rec.flags = 0;
+  rays[r] = rec;
+  nray[r] = n;
+  if (n_out) n_out[r] = n;
+}
+
+// Exclusive scan of n[R] into off[R+1] (one workgroup; R is at most a few
+// million, so a single pass of per-thread serial sums is enough).
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ n, int64_t R,
+                                                int64_t* __restrict__ off) {
+  __shared__ int64_t s[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (R + 1023) / 1024;
+  const int64_t b = t * per, e = (b + per < R) ? b + per : R;
+  int64_t acc = 0;
+  for (int64_t k = b; k < e; ++k) acc += n[k];
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t add = (t >= o) ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int64_t run = s[t] - acc;  // exclusive prefix of this thread's range
+  for (int64_t k = b; k < e; ++k) {
+    off[k] = run;
+    run += n[k];
+  }
+  if (t == 1023) off[R] = s[1023];
+}
+
+// tile_ray0[t] = ray holding point t*TILE (R when past the last point).
+__global__ void k_tiles(const int64_t* __restrict__ off, int64_t R, int tile, int64_t n_tiles_max,
+                        int32_t* __restrict__ tr0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n_tiles_max) return;
+  const int64_t p = t * tile;
+  const int64_t P = off[R];
+  if (p >= P) {
+    tr0[t] = (int32_t)R;
+    return;
+  }
+  int64_t lo = 0, hi = R - 1;  // largest r with off[r] <= p
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  tr0[t] = (int32_t)lo;
+}
+
+// ------------------------------------------------------------ packing
+//
+// Fragment of output block ob and K-chunk c for lane l, element e:
+//   Wpk[((ob*CH + c)*64 + l)*VPC + e] = W[32 ob + l%32][feat(VPC c + e, l/32)]
+// where CH = fan_in/(2 VPC).  The transposed copy used by the adjoint chain
+// packs W_l^T the same way.
+template <int PREC>
+__global__ void k_pack(PackArgs a, const float* __restrict__ P, void* __restrict__ Wpk_,
+                       void* __restrict__ WTpk_, float* __restrict__ bias,
+                       float* __restrict__ wo_perm) {
+  using T = Prec<PREC>;
+  using E = typename T::elem_t;
+  E* Wpk = (E*)Wpk_;
+  E* WTpk = (E*)WTpk_;
+  constexpr int VPC = T::VPC;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int H = a.H;
+  // forward fragments
+  if (gid < a.n_w) {
+    int l = 0;
+    while (l + 1 < a.L && gid >= a.pk_off[l + 1]) ++l;
+    const int64_t q = gid - a.pk_off[l];
+    const int fin = (l == 0) ? a.IN : H;
+    const int CH = fin / (2 * VPC);
+    const int e = (int)(q % VPC);
+    const int lane = (int)((q / VPC) % 64);
+    const int64_t fc = q / (VPC * 64);
+    const int c = (int)(fc % CH);
+    const int ob = (int)(fc / CH);
+    const int row = 32 * ob + (lane & 31);
+    const int k = feat(VPC * c + e, lane >> 5);
+    Wpk[gid] = (E)P[a.w_off[l] + (int64_t)row * fin + k];
+  }
+  // transposed fragments of layers 2..L (rows = layer input units)
+  if (gid < a.n_wt) {
+    int l = 1;
+    while (l + 1 < a.L && gid >= a.pkT_off[l + 1]) ++l;
+    const int64_t q = gid - a.pkT_off[l];
+    const int CH = H / (2 * VPC);
+    const int e = (int)(q % VPC);
+    const int lane = (int)((q / VPC) % 64);
+    const int64_t fc = q / (VPC * 64);
+    const int c = (int)(fc % CH);
+    const int ob = (int)(fc / CH);
+    const int row = 32 * ob + (lane & 31);   // input unit of layer l
+    const int k = feat(VPC * c + e, lane >> 5);  // output unit of layer l
+    WTpk[gid] = (E)P[a.w_off[l] + (int64_t)k * H + row];
+  }
+  if (gid < (int64_t)a.L * H) {
+    const int l = (int)(gid / H), r = (int)(gid % H);
+    bias[gid] = P[a.b_off[l] + r];
+  }
+  if (gid < H) {
+    const int hf = (int)(gid / (H / 2)), rho = (int)(gid % (H / 2));
+    wo_perm[gid] = P[a.wo_off + feat(rho, hf)];
+  }
+}
+
+// ------------------------------------------------------------ the MLP
+
+template <int PREC>
+__device__ inline void sincos_rev(float f, float* s, float* c) {
+  // f in [-1/2, 1/2] revolutions
+  if (PREC == PREC_BF16) {
+    *s = __builtin_amdgcn_sinf(f);
+    *c = __builtin_amdgcn_cosf(f);
+  } else {
+    sincospif(2.0f * f, s, c);
+  }
+}
+
+// One fully connected layer for the wave's NB point blocks:
+//   y = act(W x + b)   (EPI_RELU_BIAS, with ReLU mask bits written to msk)
+//   y = (W x) . mask   (EPI_MASK, mask bits read from msk)
+// W points at the layer's packed fragments; OB = H/32 output blocks.
+enum { EPI_RELU_BIAS = 0, EPI_MASK = 1 };
+
+template <int PREC, int H>
+constexpr int mask_words() { return Prec<PREC>::NB * (H / 32) / 2; }
+
+template <int PREC, int KC, int H, int EPI>
+__device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>::NB][KC],
+                             typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
+                             const typename Prec<PREC>::chunk_t* __restrict__ W,
+                             const float* __restrict__ bias, uint32_t (&msk)[mask_words<PREC, H>()],
+                             int lane) {
+  using T = Prec<PREC>;
+  constexpr int NB = T::NB, VPC = T::VPC;
+  constexpr int OB = H / 32;
+  constexpr int CPO = 16 / VPC;  // chunks per output block
+  const int hf = lane >> 5;
+  if (EPI == EPI_RELU_BIAS)
+#pragma unroll
+    for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
+#pragma unroll
+  for (int ob = 0; ob < OB; ++ob) {
+    f32x16 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+      const typename T::chunk_t wa = W[(ob * KC + c) * 64 + lane];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) T::mma(acc[nb], wa, x[nb][c]);
+    }
+    // rows of this lane: 32 ob + 8 q + 4 hf + (0..3)
+    float bq[16];
+    if (EPI == EPI_RELU_BIAS) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 b4 = *(const float4*)(bias + 32 * ob + 8 * q + 4 * hf);
+        bq[4 * q + 0] = b4.x; bq[4 * q + 1] = b4.y; bq[4 * q + 2] = b4.z; bq[4 * q + 3] = b4.w;
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      float v[16];
+      uint32_t bits = 0;
+      const int mw = (nb * OB + ob) >> 1, sh = 16 * ((nb * OB + ob) & 1);
+      if (EPI == EPI_RELU_BIAS) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const float z = acc[nb][r] + bq[r];
+          v[r] = z > 0.f ? z : 0.f;
+          bits |= (z > 0.f ? 1u : 0u) << r;
+        }
+        msk[mw] |= bits << sh;
+      } else {
+        bits = msk[mw] >> sh;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = ((bits >> r) & 1u) ? acc[nb][r] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < CPO; ++k) y[nb][ob * CPO + k] = T::from_f32(&v[k * VPC]);
+    }
+  }
+}
+
+template <int PREC, int CH>
+__device__ inline void stash_store(typename Prec<PREC>::chunk_t* __restrict__ dst,
+                                   const typename Prec<PREC>::chunk_t (&x)[CH], int lane) {
+#pragma unroll
+  for (int c = 0; c < CH; ++c) dst[c * 64 + lane] = x[c];
+}
+
+template <int PREC, int IN, int H, int MODE>
+__global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
+  using T = Prec<PREC>;
+  using chunk_t = typename T::chunk_t;
+  constexpr int NB = T::NB, VPC = T::VPC;
+  constexpr int CI = chunks<PREC>(IN), CHh = chunks<PREC>(H);
+  constexpr int TILE = WAVES_PER_WG * NB * 32;
+  constexpr int C = IN / 2;
+  constexpr int OB = H / 32;
+  constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
+  constexpr int MSK_LAYERS = (MODE == MODE_BWD) ? MAX_LAYERS - 1 : 1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hf = lane >> 5, pl = lane & 31;
+
+  __shared__ float4 sB[C];
+  __shared__ float sval[TILE];
+  __shared__ int32_t srid[TILE];
+  __shared__ float sdwo[WAVES_PER_WG][H + 1];
+  // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
+  __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
+
+  for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
+  if (MODE == MODE_BWD)
+    for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
+  __syncthreads();
+
+  const chunk_t* __restrict__ Wpk = (const chunk_t*)a.Wpk;
+  const chunk_t* __restrict__ WTpk = (const chunk_t*)a.WTpk;
+  const int64_t P = a.off[a.R];
+  const int64_t n_tiles = (P + TILE - 1) / TILE;
+  const int64_t t_end = a.tile_end < n_tiles ? a.tile_end : n_tiles;
+  const float bo = a.params[a.bo_off];
+
+  for (int64_t t = a.tile_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+    int rid[NB];
+    float wgt[NB];
+    chunk_t x0[NB][CI];
+    // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
+      float rt = 0.f, rz = 0.f, ry = 0.f, rx = 0.f;
+      rid[nb] = -1;
+      wgt[nb] = 0.f;
+      if (p < P) {
+        int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
+        if (hi > a.R - 1) hi = a.R - 1;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi + 1) >> 1;
+          if (a.off[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        const RayRec rr = a.rays[lo];
+        const float s = rr.s_in + ((float)(p - a.off[lo]) + 0.5f) * rr.dl;
+        rt = rr.tn;
+        rz = rr.pz + s * rr.dz;
+        ry = rr.py + s * rr.dy;
+        rx = rr.px + s * rr.dx;
+        rid[nb] = (int)lo;
+        wgt[nb] = rr.wgt;
+      }
+#pragma unroll
+      for (int c = 0; c < CI / 2; ++c) {
+        float cv[VPC], sv[VPC];
+#pragma unroll
+        for (int e = 0; e < VPC; ++e) {
+          const float4 b = sB[feat(VPC * c + e, hf)];
+          const float u = b.x * rt + b.y * rz + b.z * ry + b.w * rx;
+          const float f = u - rintf(u);
+          sincos_rev<PREC>(f, &sv[e], &cv[e]);
+        }
+        x0[nb][c] = T::from_f32(cv);
+        x0[nb][c + CI / 2] = T::from_f32(sv);
+      }
+    }
+    const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
+    uint32_t* msk_w = &smsk[w][0][0][0];
+    // ---- hidden layers (Appendix B item 3)
+    chunk_t y[NB][CHh];
+    if (MODE == MODE_BWD) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        stash_store<PREC, CI>((chunk_t*)a.stash + a.h_base[0] + (blk0 + nb) * (CI * 64), x0[nb],
+                              lane);
+    }
+    {
+      uint32_t mk[MSK_PER_LAYER];
+      layer<PREC, CI, H, EPI_RELU_BIAS>(x0, y, Wpk, a.bias, mk, lane);
+      if (MODE == MODE_BWD && a.L > 1)
+#pragma unroll
+        for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+    }
+    for (int l = 1; l < a.L; ++l) {
+      chunk_t xh[NB][CHh];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int c = 0; c < CHh; ++c) xh[nb][c] = y[nb][c];
+      if (MODE == MODE_BWD) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          stash_store<PREC, CHh>((chunk_t*)a.stash + a.h_base[l] + (blk0 + nb) * (CHh * 64),
+                                 xh[nb], lane);
+      }
+      uint32_t mk[MSK_PER_LAYER];
+      layer<PREC, CHh, H, EPI_RELU_BIAS>(xh, y, Wpk + a.wpk_off[l] / VPC, a.bias + l * H, mk,
+                                         lane);
+      if (MODE == MODE_BWD && l < a.L - 1)
+#pragma unroll
+        for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+    }
+    // ---- output unit (Appendix B item 4) with the configured output map
+    float zo[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
+    const float* wop = a.wo_perm + hf * (H / 2);
+#pragma unroll
+    for (int c = 0; c < CHh; ++c) {
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) {
+        const float wv = wop[VPC * c + e];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) zo[nb] += wv * T::get(y[nb][c], e);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) zo[nb] += __shfl_xor(zo[nb], 32) + bo;
+
+    if (MODE == MODE_FWD) {
+      // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float z = zo[nb];
+        const float M = a.out_act ? fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) : z;
+        if (hf == 0) {
+          const int tp = w * (NB * 32) + nb * 32 + pl;
+          sval[tp] = rid[nb] >= 0 ? M : 0.f;
+          srid[tp] = rid[nb];
+        }
+      }
+      __syncthreads();
+      const int tp = threadIdx.x;
+      for (int o = 1; o < TILE; o <<= 1) {
+        float add = 0.f;
+        if (tp < TILE && tp >= o && srid[tp - o] == srid[tp]) add = sval[tp - o];
+        __syncthreads();
+        if (tp < TILE) sval[tp] += add;
+        __syncthreads();
+      }
+      if (tp < TILE) {
+        const int r = srid[tp];
+        if (r >= 0 && (tp == TILE - 1 || srid[tp + 1] != r)) {
+          const int64_t o0 = a.off[r];
+          const int64_t o1 = a.off[r + 1];
+          const int64_t tb = t * TILE;
+          const float sum = sval[tp];
+          if (o0 < tb) a.part[2 * t + 0] = sum;
+          else if (o1 > tb + TILE) a.part[2 * t + 1] = sum;
+          else a.proj[r] = a.rays[r].wgt * sum;
+        }
+      }
+      __syncthreads();
+    } else {
+      // ---- adjoint (Eq. (8)): dL/dM = g_r mu0 l_r / n_r, through the output map
+      float dob[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const float z = zo[nb];
+        const float dMdz = a.out_act ? 1.f / (1.f + expf(-z)) : 1.f;
+        dob[nb] = rid[nb] >= 0 ? a.gup[rid[nb]] * wgt[nb] * dMdz : 0.f;
+      }
+      // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
+      // Halving butterfly over the 32 lanes of each half: after 5 steps lane
+      // pl holds the sums of slots 4 pl .. 4 pl + 3.
+      {
+        constexpr int K = H / 2;
+        float v[K];
+#pragma unroll
+        for (int c = 0; c < CHh; ++c)
+#pragma unroll
+          for (int e = 0; e < VPC; ++e) {
+            float s = 0.f;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][c], e);
+            v[VPC * c + e] = s;
+          }
+#pragma unroll
+        for (int st = 0; st < 5; ++st) {
+          const int o = 16 >> st;
+          const int half = K >> (st + 1);
+          const bool up = (pl & o) != 0;
+#pragma unroll
+          for (int i = 0; i < half; ++i) {
+            const float send = up ? v[i] : v[i + half];
+            const float keep = up ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, o);
+          }
+        }
+        constexpr int KF = K / 32;
+        const int f0 = feat(KF * pl, hf);
+#pragma unroll
+        for (int i = 0; i < KF; ++i) sdwo[w][f0 + i] += v[i];
+        float sb = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) sb += dob[nb];
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
+        if (lane == 0) sdwo[w][H] += sb;
+      }
+      // delta_L = w_o dob . relu'(z_L)
+      chunk_t d[NB][CHh];
+#pragma unroll
+      for (int c = 0; c < CHh; ++c) {
+        float wv[VPC];
+#pragma unroll
+        for (int e = 0; e < VPC; ++e) wv[e] = wop[VPC * c + e];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float v[VPC];
+#pragma unroll
+          for (int e = 0; e < VPC; ++e) v[e] = T::get(y[nb][c], e) > 0.f ? wv[e] * dob[nb] : 0.f;
+          d[nb][c] = T::from_f32(v);
+        }
+      }
+      const int L = a.L;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        stash_store<PREC, CHh>((chunk_t*)a.stash + a.d_base[L - 1] + (blk0 + nb) * (CHh * 64), d[nb],
+                               lane);
+      // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2
+      for (int l = L - 1; l >= 1; --l) {
+        uint32_t mk[MSK_PER_LAYER];
+#pragma unroll
+        for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
+        chunk_t dn[NB][CHh];
+        layer<PREC, CHh, H, EPI_MASK>(d, dn, WTpk + a.wtpk_off[l] / VPC, nullptr, mk, lane);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+          for (int c = 0; c < CHh; ++c) d[nb][c] = dn[nb][c];
+          stash_store<PREC, CHh>((chunk_t*)a.stash + a.d_base[l - 1] + (blk0 + nb) * (CHh * 64),
+                                 d[nb], lane);
+        }
+      }
+    }
+  }
+  if (MODE == MODE_BWD) {
+    __syncthreads();
+    for (int f = threadIdx.x; f <= H; f += blockDim.x) {
+      float s = 0.f;
+      for (int ww = 0; ww < WAVES_PER_WG; ++ww) s += sdwo[ww][f];
+      a.opart[(int64_t)blockIdx.x * (H + 1) + f] = s;
+    }
+  }
+}
+
+// Ray-sums of rays that span tiles: compensated sum of the tile partials in
+// tile order.  Also writes projections of empty rays (0) and of rays with an
+// out-of-range index (NaN).
+__global__ void k_fixup(const RayRec* __restrict__ rays, const int64_t* __restrict__ off, int64_t R,
+                        int tile, const float* __restrict__ part, float* __restrict__ proj) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const RayRec rr = rays[r];
+  if (rr.flags & 1) { proj[r] = __builtin_nanf(""); return; }
+  if (rr.n == 0) { proj[r] = 0.f; return; }
+  const int64_t o0 = off[r], o1 = off[r + 1];
+  const int64_t t0 = o0 / tile, t1 = (o1 - 1) / tile;
+  if (t0 == t1) return;
+  float s = part[2 * t0 + 1], comp = 0.f;
+  for (int64_t k = t0 + 1; k <= t1; ++k) {
+    const float y = part[2 * k] - comp;
+    const float tt = s + y;
+    comp = (tt - s) - y;
+    s = tt;
+  }
+  proj[r] = rr.wgt * s;
+}
+
+// Loss (Eq. (5)) in FP64 and the upstream gradient g_r = 2 (pbar_r - p_r) / R.
+// One workgroup, fixed summation order.
+__global__ __launch_bounds__(1024) void k_loss(const float* __restrict__ proj,
+                                                const float* __restrict__ meas, int64_t R,
+                                                float* __restrict__ g, double* __restrict__ loss) {
+  __shared__ double s[1024];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  const float inv = 2.0f / (float)R;
+  for (int64_t r = t; r < R; r += 1024) {
+    const float e = proj[r] - meas[r];
+    acc += (double)e * (double)e;
+    g[r] = inv * e;
+  }
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) s[t] += s[t + o];
+    __syncthreads();
+  }
+  if (t == 0) *loss = s[0] / (double)R;
+}
+
+// ------------------------------------------------------------ dW
+
+// dW_l[o][i] = sum_p delta_l[p][o] h_{l-1}[p][i]  (and db_l = sum_p delta_l[p])
+// over the stash blocks of one split.  The stash holds blocks of 32 points in
+// the register layout of k_mlp; each block is transposed through LDS into
+// [feature][point] rows so that both matrix-core operands are read as 16-byte
+// runs of consecutive points (K = points).
+template <int PREC, int FI, int H>
+__global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
+  using T = Prec<PREC>;
+  using E = typename T::elem_t;
+  using chunk_t = typename T::chunk_t;
+  constexpr int VPC = T::VPC;
+  constexpr int CHd = chunks<PREC>(H), CHi = chunks<PREC>(FI);
+  constexpr int ROW = 32 + 16 / (int)sizeof(E);  // padded row (elements)
+  constexpr int RB = H / 32, CB = FI / 32, NT = RB * CB;
+  constexpr int NW = 8;
+  constexpr int TPW = (NT + NW - 1) / NW;
+  __shared__ __align__(16) E sD[H * ROW];
+  __shared__ __align__(16) E sH[FI * ROW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hf = lane >> 5;
+  const int s = a.layer;
+
+  const int64_t P = a.off[a.R];
+  const int64_t n_tiles = (P + a.tile - 1) / a.tile;
+  int64_t pend = n_tiles * a.tile;
+  if (pend > a.chunk_p1) pend = a.chunk_p1;
+  const int64_t nblk = (pend - a.chunk_p0) / 32;
+  const int64_t b0 = (int64_t)blockIdx.x * a.kb;
+  int64_t b1 = b0 + a.kb;
+  if (b1 > nblk) b1 = nblk;
+  if (b0 >= b1) return;
+
+  f32x16 acc[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+  float dbacc = 0.f;
+
+  const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
+  const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
+
+  for (int64_t b = b0; b < b1; ++b) {
+    __syncthreads();
+    for (int q = tid; q < CHd * 64; q += 512) {
+      const chunk_t v = Dst[b * (CHd * 64) + q];
+      const int c = q >> 6, l = q & 63;
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) sD[feat(VPC * c + e, l >> 5) * ROW + (l & 31)] = (E)T::get(v, e);
+    }
+    for (int q = tid; q < CHi * 64; q += 512) {
+      const chunk_t v = Hst[b * (CHi * 64) + q];
+      const int c = q >> 6, l = q & 63;
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + (l & 31)] = (E)T::get(v, e);
+    }
+    __syncthreads();
+    if (tid < H) {
+      float sb = 0.f;
+#pragma unroll
+      for (int p = 0; p < 32; ++p) sb += (float)sD[tid * ROW + p];
+      dbacc += sb;
+    }
+#pragma unroll
+    for (int k = 0; k < TPW; ++k) {
+      const int tix = w + NW * k;
+      if (tix < NT) {
+        const int rb = tix / CB, cb = tix % CB;
+        const E* ra = sD + (32 * rb + (lane & 31)) * ROW;
+        const E* rbp = sH + (32 * cb + (lane & 31)) * ROW;
+        if (PREC == PREC_BF16) {
+#pragma unroll
+          for (int st = 0; st < 2; ++st) {
+            const chunk_t av = *(const chunk_t*)(ra + 16 * st + 8 * hf);
+            const chunk_t bv = *(const chunk_t*)(rbp + 16 * st + 8 * hf);
+            T::mma(acc[k], av, bv);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const chunk_t av = *(const chunk_t*)(ra + 16 * hf + 4 * q);
+            const chunk_t bv = *(const chunk_t*)(rbp + 16 * hf + 4 * q);
+            T::mma(acc[k], av, bv);
+          }
+        }
+      }
+    }
+  }
+  // partial row of this split: same layout as the hidden part of the gradient
+  float* out = a.wpart + (a.split_base + blockIdx.x) * a.nh;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    const int tix = w + NW * k;
+    if (tix < NT) {
+      const int rb = tix / CB, cb = tix % CB;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
+        out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] = acc[k][r];
+      }
+    }
+  }
+  if (tid < H) out[a.b_off + tid] = dbacc;
+}
+
+// grad[k] = compensated sum over valid split partials (hidden layers) or over
+// the per-workgroup output-layer partials; per-block FP64 sums of grad^2.
+__global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
+  __shared__ double s[256];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (k < a.np) {
+    float sum = 0.f, comp = 0.f;
+    if (k < a.nh) {
+      const int64_t P = a.off[a.R];
+      const int64_t n_tiles = (P + a.tile - 1) / a.tile;
+      const int64_t pend = n_tiles * a.tile;
+      for (int64_t c = 0; c < a.n_chunks; ++c) {
+        const int64_t p0 = c * a.chunk_points;
+        if (p0 >= pend) break;
+        const int64_t pe = (pend < p0 + a.chunk_points) ? pend : p0 + a.chunk_points;
+        const int64_t nblk = (pe - p0) / 32;
+        const int64_t nsp = (nblk + a.kb - 1) / a.kb;
+        for (int64_t i = 0; i < nsp; ++i) {
+          const float y = a.wpart[(c * a.splits_per_chunk + i) * a.nh + k] - comp;
+          const float t = sum + y;
+          comp = (t - sum) - y;
+          sum = t;
+        }
+      }
+    } else {
+      const int64_t j = k - a.nh;
+      for (int64_t i = 0; i < a.n_opart; ++i) {
+        const float y = a.opart[i * a.no + j] - comp;
+        const float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+      }
+    }
+    a.grad[k] = sum;
+    sq = (double)sum * (double)sum;
+  }
+  s[threadIdx.x] = sq;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.gn_part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_gnorm(const double* __restrict__ gn_part, int64_t n,
+                                               double* __restrict__ gnorm_ws,
+                                               double* __restrict__ gnorm_out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) acc += gn_part[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *gnorm_ws = s[0];
+    if (gnorm_out) *gnorm_out = s[0];
+  }
+}
+
+// Adam (bias-corrected) on the flat parameters, skipped when the loss or the
+// gradient norm is not finite; status[0] = 1 records the skip.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2, const double* __restrict__ loss,
+                       const double* __restrict__ gnorm, int32_t* __restrict__ status) {
+  const double L = *loss, G = *gnorm;
+  const bool ok = isfinite(L) && isfinite(G);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0) status[0] = ok ? 0 : 1;
+  if (!ok || k >= n) return;
+  const float gk = g[k];
+  const float mk = b1 * m[k] + (1.f - b1) * gk;
+  const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+  m[k] = mk;
+  v[k] = vk;
+  p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// ------------------------------------------------------------ launchers
+
+#define DINR_SHAPES(X) X(128, 64) X(256, 256)
+
+template <int PREC>
+static hipError_t pack_impl(const PackArgs& a, const float* P, void* Wpk, void* WTpk, float* bias,
+                            float* wo, hipStream_t st) {
+  int64_t n = a.n_w;
+  if (a.n_wt > n) n = a.n_wt;
+  if ((int64_t)a.L * a.H > n) n = (int64_t)a.L * a.H;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_pack<PREC>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, a, P, Wpk,
+                     WTpk, bias, wo);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, void* WTpk,
+                       float* bias, float* wo, hipStream_t st) {
+  return prec == PREC_BF16 ? pack_impl<PREC_BF16>(a, P, Wpk, WTpk, bias, wo, st)
+                           : pack_impl<PREC_F32>(a, P, Wpk, WTpk, bias, wo, st);
+}
+
+hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* rays, int32_t* nray,
+                       int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
+                       hipStream_t st) {
+  const int bs = 256;
+  if (R > 0)
+    hipLaunchKernelGGL(k_rays, dim3((unsigned)((R + bs - 1) / bs)), dim3(bs), 0, st, g, idx, R, rays,
+                       nray, n_out);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nray, R, off);
+  hipLaunchKernelGGL(k_tiles, dim3((unsigned)((n_tiles_max + 1 + bs - 1) / bs)), dim3(bs), 0, st,
+                     off, R, tile, n_tiles_max, tr0);
+  return hipGetLastError();
+}
+
+template <int PREC, int IN, int H>
+static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st) {
+  if (mode == MODE_FWD)
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD>), dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int grid,
+                      hipStream_t st) {
+#define X(I, HH)                                                                   \
+  if (in == I && h == HH)                                                          \
+    return prec == PREC_BF16 ? mlp_impl<PREC_BF16, I, HH>(mode, a, grid, st)       \
+                             : mlp_impl<PREC_F32, I, HH>(mode, a, grid, st);
+  DINR_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int tile,
+                        const float* part, float* proj, hipStream_t st) {
+  if (R == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fixup, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, rays, off, R, tile,
+                     part, proj);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, st, proj, meas, R, g, loss);
+  return hipGetLastError();
+}
+
+template <int PREC, int FI, int H>
+static hipError_t wgrad_impl(const WgArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_wgrad<PREC, FI, H>), dim3(grid), dim3(512), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
+#define X(I, HH)                                                                  \
+  if (h == HH && fi == I)                                                         \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH>(a, grid, st)          \
+                             : wgrad_impl<PREC_F32, I, HH>(a, grid, st);          \
+  if (h == HH && fi == HH)                                                        \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, HH, HH>(a, grid, st)         \
+                             : wgrad_impl<PREC_F32, HH, HH>(a, grid, st);
+  DINR_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const RedArgs& a, double* gnorm_ws, double* gnorm_out, hipStream_t st) {
+  const unsigned nblk = (unsigned)((a.np + 255) / 256);
+  hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(256), 0, st, a.gn_part, (int64_t)nblk, gnorm_ws,
+                     gnorm_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2, const double* loss,
+                       const double* gnorm, int32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr,
+                     b1, b2, eps, c1, c2, loss, gnorm, status);
+  return hipGetLastError();
+}
+
+}  // namespace dinr

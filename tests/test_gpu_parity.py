@@ -1,0 +1,259 @@
+"""GPU path vs the FP64 oracle, element by element, on the same seeded inputs.
+
+Tolerances (norm-wise relative error, ||x - x_ref|| / ||x_ref||):
+  FP32 path: projections 1e-4, every gradient tensor 1e-3, loss 1e-4
+  BF16 path: projections 2e-2 (gradients and loss are reported and held to a
+             loose sanity bound of 5e-2)
+Sample counts are integers and must match exactly wherever the chord length
+is not within 1e-4 (relative) of a multiple of the step; the oracle is then
+re-run with the GPU's counts so that projections are compared on equal
+quadratures.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_19075_amd import synth as S
+
+from helpers import log, make_ctx, param_slices, rel, small_workload
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = 0, 1
+TOL_PROJ = {FP32: 1e-4, BF16: 2e-2}
+TOL_GRAD = {FP32: 1e-3, BF16: 5e-2}
+
+
+def run_forward(w, batch, prec):
+    ctx = make_ctx(w, batch.B, prec)
+    P = torch.tensor(batch.params, device="cuda")
+    idx = torch.tensor(batch.idx, device="cuda")
+    n = torch.empty(len(batch.idx), dtype=torch.int32, device="cuda")
+    proj = ctx.forward_project(P, idx, n_out=n)
+    torch.cuda.synchronize()
+    out = proj.cpu().numpy(), n.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def run_step(w, batch, prec, adam=None):
+    ctx = make_ctx(w, batch.B, prec)
+    P = torch.tensor(batch.params, device="cuda")
+    idx = torch.tensor(batch.idx, device="cuda")
+    meas = torch.tensor(batch.meas, device="cuda")
+    proj = torch.empty(len(batch.idx), dtype=torch.float32, device="cuda")
+    grad, proj, loss, gnorm = ctx.step(P, idx, meas, proj=proj, adam=adam)
+    torch.cuda.synchronize()
+    out = dict(grad=grad.cpu().numpy(), proj=proj.cpu().numpy(), loss=float(loss.item()),
+               gnorm=float(gnorm.item()), params=P.cpu().numpy(), status=ctx.step_status())
+    ctx.close()
+    return out
+
+
+_ORACLE = {}
+
+
+def oracle_step(key, w, b, n_override=None):
+    """Oracle (loss, grad, proj), computed once per workload key."""
+    if key not in _ORACLE:
+        _ORACLE[key] = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas,
+                              n_override=n_override)
+    return _ORACLE[key]
+
+
+def check_grad(w, g, ref, tol, label):
+    worst = 0.0
+    for name, sl in param_slices(w.mlp):
+        e = rel(g[sl], ref[sl])
+        worst = max(worst, e)
+        log(f"  {label} {name}: rel err {e:.3e}")
+        assert e <= tol, (label, name, e)
+    return worst
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_forward_c0(prec):
+    b = S.make_batch("c0")
+    w = b.workload
+    log(f"test_forward_c0 prec={prec} R={len(b.idx)}")
+    proj, n = run_forward(w, b, prec)
+    ref, nref, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx)
+    assert np.array_equal(n, nref)
+    e = rel(proj, ref)
+    log(f"  proj rel err {e:.3e}")
+    assert e <= TOL_PROJ[prec]
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_step_c0(prec):
+    b = S.make_batch("c0")
+    w = b.workload
+    log(f"test_step_c0 prec={prec}")
+    out = run_step(w, b, prec)
+    loss, grad, proj = oracle_step("c0", w, b)
+    ep = rel(out["proj"], proj)
+    el = abs(out["loss"] - loss) / loss
+    log(f"  proj {ep:.3e} loss {el:.3e} (gpu {out['loss']:.6e} oracle {loss:.6e})")
+    assert ep <= TOL_PROJ[prec]
+    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c0 prec={prec}")
+    gn = float(np.sum(out["grad"].astype(np.float64) ** 2))
+    assert abs(out["gnorm"] - gn) <= 1e-9 * gn
+    assert out["status"] == 0
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_c1_network_ray_subset(prec):
+    """The c1/c2 network (2C = 256, H = 256, L = 6) and geometry (256^2
+    detector, 720 views, 256 samples per ray) on a ray subset the oracle
+    finishes in seconds; 160 rays span many point tiles and a ragged last
+    weight-gradient split."""
+    w = small_workload("c1", 160)
+    b = S.make_batch(w)
+    log(f"test_c1_network_ray_subset prec={prec} R={len(b.idx)}")
+    out = run_step(w, b, prec)
+    loss, grad, proj = oracle_step("c1-160", w, b)
+    ep = rel(out["proj"], proj)
+    log(f"  proj {ep:.3e} loss gpu {out['loss']:.6e} oracle {loss:.6e}")
+    assert ep <= TOL_PROJ[prec]
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c1 prec={prec}")
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_cone_ragged_subset(prec):
+    """c3 geometry and network (cone beam, n = clamp(ceil(l/h), 32, 512),
+    L = 8) on 96 rays: rays span tile boundaries in the forward ray-sum."""
+    w = small_workload("c3", 96)
+    b = S.make_batch(w)
+    log(f"test_cone_ragged_subset prec={prec}")
+    proj_g, n_g = run_forward(w, b, prec)
+    _, n_ref, _, ln = O.forward(w.geom, w.mlp, w.sampling, None, None, b.idx, field=(1, (0, 0, 0, 0, 0)))
+    q = ln / w.sampling.h
+    near_tie = np.abs(q - np.round(q)) < 1e-4 * np.maximum(q, 1)
+    log(f"  n mismatches {int(np.sum(n_g != n_ref))}, near ties {int(near_tie.sum())}, "
+        f"n range {n_g.min()}..{n_g.max()}")
+    assert np.all((n_g == n_ref) | near_tie)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, n_override=n_g)
+    ep = rel(proj_g, ref)
+    log(f"  proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[prec]
+    out = run_step(w, b, prec)
+    loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas, n_override=n_g)
+    log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e}")
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 prec={prec}")
+
+
+def test_adam_update_c0():
+    b = S.make_batch("c0")
+    w = b.workload
+    m = torch.zeros(w.mlp.n_params, device="cuda")
+    v = torch.zeros(w.mlp.n_params, device="cuda")
+    out = run_step(w, b, FP32, adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, 1))
+    _, grad, _ = oracle_step("c0", w, b)
+    p = b.params.astype(np.float64)
+    mm, vv = np.zeros_like(p), np.zeros_like(p)
+    O.adam(p, grad, mm, vv, 1e-3, 0.9, 0.999, 1e-8, 1)
+    # step 1 moves each weight by ~lr sign(g): compare where |g| is not tiny
+    mask = np.abs(grad) > 1e-6 * np.abs(grad).max()
+    err = np.abs(out["params"].astype(np.float64) - p)[mask].max()
+    log(f"  adam max abs err {err:.3e} on {mask.sum()} params")
+    assert err <= 1e-6
+
+
+def test_edges_misses_bad_indices_and_small_batches():
+    w = S.workload("c0")
+    b = S.make_batch("c0")
+    g = w.geom
+    # pixel 0 of view 0 sits at |u| = |v| = 1.45 > 1: its ray misses the box
+    idx = np.array([0, b.idx[0], g.n_proj + 5, -1, b.idx[1]], dtype=np.int64)
+    bb = dataclasses.replace(b, idx=idx, meas=np.zeros(5, np.float32))
+    proj, n = run_forward(w, bb, FP32)
+    log(f"  edge proj {proj} n {n}")
+    assert proj[0] == 0.0 and n[0] == 0
+    assert np.isnan(proj[2]) and np.isnan(proj[3])
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, idx[[1, 4]])
+    assert rel(proj[[1, 4]], ref) <= 1e-4
+    for R in (1, 3, 5):
+        bb = dataclasses.replace(b, idx=b.idx[:R], meas=b.meas[:R])
+        proj, _ = run_forward(w, bb, BF16)
+        ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx[:R])
+        assert rel(proj, ref) <= 2e-2
+
+
+def test_nonfinite_measurement_skips_adam():
+    b = S.make_batch("c0")
+    w = b.workload
+    meas = b.meas.copy()
+    meas[7] = np.nan
+    bb = dataclasses.replace(b, meas=meas)
+    m = torch.zeros(w.mlp.n_params, device="cuda")
+    v = torch.zeros(w.mlp.n_params, device="cuda")
+    out = run_step(w, bb, FP32, adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, 1))
+    assert out["status"] == -4
+    assert np.array_equal(out["params"], b.params)
+
+
+def test_run_to_run_bitwise_determinism():
+    w = small_workload("c1", 160)
+    b = S.make_batch(w)
+    o1 = run_step(w, b, BF16)
+    o2 = run_step(w, b, BF16)
+    assert np.array_equal(o1["grad"], o2["grad"]) and np.array_equal(o1["proj"], o2["proj"])
+    assert o1["loss"] == o2["loss"]
+
+
+def test_batch_additivity_full_c1_size():
+    """At the full c1 batch (65,536 rays x 256 samples), the gradient of the
+    whole batch equals the size-weighted mean of the gradients of its halves
+    (the averaging of Sec. II), and the projections of 48 sampled rays match
+    the oracle one by one."""
+    w = S.workload("c2")
+    b = S.make_batch(w)
+    log(f"full c1 size: R={len(b.idx)}")
+    ctx = make_ctx(w, b.B, BF16, ws_bytes=64 << 30)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    proj = torch.empty(len(b.idx), device="cuda")
+    gfull, _, _, _ = ctx.step(P, idx, meas, proj=proj)
+    h = len(b.idx) // 2
+    # per-half gradients with the full-batch normalisation: dL/dpbar = 2 e / R
+    g1 = ctx.project_backward(P, idx[:h].contiguous(),
+                              (2.0 / len(b.idx)) * (proj[:h] - meas[:h]).contiguous())
+    g2 = ctx.project_backward(P, idx[h:].contiguous(),
+                              (2.0 / len(b.idx)) * (proj[h:] - meas[h:]).contiguous())
+    torch.cuda.synchronize()
+    gf = gfull.cpu().numpy().astype(np.float64)
+    gs = (g1.cpu().numpy().astype(np.float64) + g2.cpu().numpy().astype(np.float64))
+    e = rel(gs, gf)
+    log(f"  additivity rel err {e:.3e}")
+    assert e <= 1e-5
+    rng = np.random.default_rng(0)
+    pick = rng.choice(len(b.idx), 48, replace=False)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx[pick])
+    ep = rel(proj.cpu().numpy()[pick], ref)
+    log(f"  sampled proj rel err {ep:.3e}")
+    assert ep <= 2e-2
+    ctx.close()
+
+
+def test_autograd_function_matches_adjoint():
+    from paper_2404_19075_amd import dinr
+    w = S.workload("c0")
+    b = S.make_batch("c0")
+    ctx = make_ctx(w, b.B, FP32)
+    P = torch.tensor(b.params, device="cuda", requires_grad=True)
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    Fn = dinr.project_function()
+    pbar = Fn.apply(P, idx, ctx)
+    loss = torch.mean((meas - pbar) ** 2)
+    loss.backward()
+    grad, _, loss2, _ = ctx.step(P.detach(), idx, meas)
+    torch.cuda.synchronize()
+    assert rel(P.grad.cpu().numpy(), grad.cpu().numpy()) <= 1e-5
+    assert abs(loss.item() - loss2.item()) <= 1e-6 * loss2.item()
+    ctx.close()
