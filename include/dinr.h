@@ -170,6 +170,22 @@ int dinr_step(dinr_ctx* ctx, float* params_d, const int64_t* proj_idx_d, int64_t
  * requested, was then skipped), else DINR_OK. */
 int dinr_step_status(dinr_ctx* ctx, void* stream);
 
+/* Kernel timing (a tracing aid, off by default).  While enabled, every
+ * launch of the kernels below is bracketed by a pair of HIP events recorded
+ * on the call's stream (at most 4096 launches per kind between reads).
+ * dinr_profile_read waits for the recorded events, returns the summed
+ * duration in milliseconds and the number of launches of `kind`, and clears
+ * them.  Enabling creates the events (host-side HIP objects; no device
+ * memory). */
+enum {
+  DINR_PROF_MLP_FWD = 0,  /* fused forward: coordinates, encoding, MLP, ray-sum */
+  DINR_PROF_MLP_BWD = 1,  /* recomputed forward and adjoint chain, operand stash */
+  DINR_PROF_WGRAD = 2,    /* weight-gradient reduction over the stash */
+  DINR_PROF_KINDS = 3
+};
+int dinr_profile_enable(dinr_ctx* ctx, int enable);
+int dinr_profile_read(dinr_ctx* ctx, int kind, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,34 @@ struct dinr_ctx {
   double* d_scal = nullptr;     // [0] loss, [1] gnorm
   char err[512] = {0};
   GeomDev gd{};
+  // optional per-kernel timing: event pairs recorded around launches
+  struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> ev[DINR_PROF_KINDS][2];
+    size_t used[DINR_PROF_KINDS] = {0};
+  } prof;
+};
+
+// Record a start/stop event pair around one launch of kernel class k.
+struct ProfScope {
+  dinr_ctx* c;
+  int k;
+  hipStream_t st;
+  bool active = false;
+  ProfScope(dinr_ctx* c_, int k_, hipStream_t st_) : c(c_), k(k_), st(st_) {
+    auto& p = c->prof;
+    if (p.on && p.used[k] < p.ev[k][0].size()) {
+      hipEventRecord(p.ev[k][0][p.used[k]], st);
+      active = true;
+    }
+  }
+  ~ProfScope() {
+    if (active) {
+      auto& p = c->prof;
+      hipEventRecord(p.ev[k][1][p.used[k]], st);
+      ++p.used[k];
+    }
+  }
 };
 
 static int fail(dinr_ctx* c, int code, const char* fmt, ...) {
@@ -231,8 +259,11 @@ static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
                         p.bias, p.wo, st));
   MlpArgs a = mlp_args(c, p, params);
   a.proj = proj;
-  HIPCHK(c, launch_mlp(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, c->IN, c->H, MODE_FWD, a,
-                       p.grid_mlp, st));
+  {
+    ProfScope ps(c, DINR_PROF_MLP_FWD, st);
+    HIPCHK(c, launch_mlp(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, c->IN, c->H, MODE_FWD, a,
+                         p.grid_mlp, st));
+  }
   HIPCHK(c, launch_fixup(p.rays, p.off, p.R, c->tile, p.part, proj, st));
   return DINR_OK;
 }
@@ -254,7 +285,10 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       a.d_base[l] = p.d_base[l];
     }
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
-    HIPCHK(c, launch_mlp(prec, c->IN, c->H, MODE_BWD, a, p.grid_mlp, st));
+    {
+      ProfScope ps(c, DINR_PROF_MLP_BWD, st);
+      HIPCHK(c, launch_mlp(prec, c->IN, c->H, MODE_BWD, a, p.grid_mlp, st));
+    }
     for (int l = 0; l < c->L; ++l) {
       WgArgs w{};
       w.off = p.off;
@@ -272,6 +306,7 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       w.w_off = c->w_off[l];
       w.b_off = c->b_off[l];
       w.layer = l;
+      ProfScope ps(c, DINR_PROF_WGRAD, st);
       HIPCHK(c, launch_wgrad(prec, l == 0 ? c->IN : c->H, c->H, w, (int)p.splits_per_chunk, st));
     }
   }
@@ -463,6 +498,9 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
 
 int dinr_destroy(dinr_ctx* c) {
   if (!c) return DINR_OK;
+  for (int k = 0; k < DINR_PROF_KINDS; ++k)
+    for (int j = 0; j < 2; ++j)
+      for (auto& e : c->prof.ev[k][j]) hipEventDestroy(e);
   hipFree(c->d_cth);
   hipFree(c->d_sth);
   hipFree(c->d_tn);
@@ -473,6 +511,37 @@ int dinr_destroy(dinr_ctx* c) {
 }
 
 const char* dinr_last_error(const dinr_ctx* c) { return c ? c->err : "null context"; }
+
+int dinr_profile_enable(dinr_ctx* c, int enable) {
+  if (!c) return DINR_EINVAL;
+  auto& p = c->prof;
+  if (enable && p.ev[0][0].empty()) {
+    for (int k = 0; k < DINR_PROF_KINDS; ++k)
+      for (int j = 0; j < 2; ++j) {
+        p.ev[k][j].resize(4096);
+        for (auto& e : p.ev[k][j]) HIPCHK(c, hipEventCreate(&e));
+      }
+  }
+  p.on = enable != 0;
+  for (int k = 0; k < DINR_PROF_KINDS; ++k) p.used[k] = 0;
+  return DINR_OK;
+}
+
+int dinr_profile_read(dinr_ctx* c, int kind, double* total_ms, int64_t* launches) {
+  if (!c || kind < 0 || kind >= DINR_PROF_KINDS || !total_ms || !launches) return DINR_EINVAL;
+  auto& p = c->prof;
+  double t = 0.0;
+  for (size_t i = 0; i < p.used[kind]; ++i) {
+    HIPCHK(c, hipEventSynchronize(p.ev[kind][1][i]));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, p.ev[kind][0][i], p.ev[kind][1][i]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)p.used[kind];
+  p.used[kind] = 0;
+  return DINR_OK;
+}
 
 int64_t dinr_num_params(const dinr_ctx* c) { return c ? c->np : -1; }
 

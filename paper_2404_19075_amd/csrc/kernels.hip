@@ -251,80 +251,171 @@ __device__ inline void sincos_rev(float f, float* s, float* c) {
   }
 }
 
+// ---- weight panels in LDS
+//
+// Every layer's packed fragments are streamed through two LDS buffers of
+// PANEL_BYTES in "panels" of OBP output blocks: while the wave computes one
+// panel, the workgroup's global->LDS DMA (global_load_lds_dwordx4) fills the
+// other with the next panel of the sequence (the next layer's first panel at
+// the end of a layer, the first layer of the next tile at the end of a tile).
+// One barrier per panel: after it, the panel just waited for is visible to
+// all waves and the other buffer is no longer being read.
+constexpr int PANEL_BYTES = 32768;
+
+template <int KC, int H>
+__host__ __device__ constexpr int panel_obs() {
+  return (PANEL_BYTES / (KC * 1024)) > H / 32 ? H / 32
+         : (PANEL_BYTES / (KC * 1024)) < 1     ? 1
+                                                : PANEL_BYTES / (KC * 1024);
+}
+template <int KC, int H>
+__host__ __device__ constexpr int panel_bytes() { return panel_obs<KC, H>() * KC * 1024; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// bytes: a multiple of 4 KB (256 threads x 16 B).  Wave w copies the 1 KB
+// blocks w, w+4, ...; the LDS destination of one instruction is wave-uniform.
+__device__ inline void dma_panel(const char* __restrict__ src, char* dst, int bytes, int w,
+                                 int lane) {
+  for (int off = w * 1024; off < bytes; off += 4096)
+    __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 16), (lds_void*)(dst + off),
+                                     16, 0, 0);
+}
+
+__device__ inline void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // One fully connected layer for the wave's NB point blocks:
-//   y = act(W x + b)   (EPI_RELU_BIAS, with ReLU mask bits written to msk)
-//   y = (W x) . mask   (EPI_MASK, mask bits read from msk)
-// W points at the layer's packed fragments; OB = H/32 output blocks.
+//   y = act(W x + b)   (EPI_RELU_BIAS; ReLU mask bits go to msk)
+//   y = (W x) . mask   (EPI_MASK; mask bits come from msk)
+// W: the layer's packed fragments in global memory, streamed through LDS.
+// Wnext/next_bytes: first panel of whatever follows in the sequence (or null).
+// stash (nullable): where to store x for the weight gradient.
 enum { EPI_RELU_BIAS = 0, EPI_MASK = 1 };
 
 template <int PREC, int H>
-constexpr int mask_words() { return Prec<PREC>::NB * (H / 32) / 2; }
+__host__ __device__ constexpr int mask_words() { return Prec<PREC>::NB * (H / 32) / 2; }
 
+// Epilogue of one 16-byte chunk of an output block: ReLU (recording mask
+// bits) or the stored mask applied, then conversion to the operand type.
+template <int PREC, int H, int EPI>
+__device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, int k,
+                                 typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
+                                 uint32_t (&msk)[mask_words<PREC, H>()]) {
+  using T = Prec<PREC>;
+  constexpr int VPC = T::VPC, CPO = 16 / VPC, OB = H / 32;
+  const int nb = k / CPO, kk = k % CPO;
+  const int g = nb * OB + ob;
+  const int mw = g >> 1, sh = 16 * (g & 1) + kk * VPC;
+  float v[VPC];
+  if (EPI == EPI_RELU_BIAS) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int e = 0; e < VPC; ++e) {
+      const float zv = acc[nb][kk * VPC + e];
+      v[e] = zv > 0.f ? zv : 0.f;
+      bits |= (zv > 0.f ? 1u : 0u) << e;
+    }
+    msk[mw] |= bits << sh;
+  } else {
+    const uint32_t bits = msk[mw] >> sh;
+#pragma unroll
+    for (int e = 0; e < VPC; ++e) v[e] = ((bits >> e) & 1u) ? acc[nb][kk * VPC + e] : 0.f;
+  }
+  y[nb][ob * CPO + kk] = T::from_f32(v);
+}
+
+// One fully connected layer for the wave's NB point blocks:
+//   y = act(W x + b)   (EPI_RELU_BIAS; ReLU mask bits go to msk)
+//   y = (W x) . mask   (EPI_MASK; mask bits come from msk)
+// W: the layer's packed fragments in global memory, streamed through LDS.
+// Wnext/next_bytes: first panel of whatever follows in the sequence (or null).
+// stash (nullable): where to store x for the weight gradient.
+// Instruction stream per K-step: 2 MFMAs (one per point block), one LDS read
+// of the fragment D steps ahead, and a slice of the previous output block's
+// epilogue, so VALU work and LDS latency overlap the matrix cores.
 template <int PREC, int KC, int H, int EPI>
 __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>::NB][KC],
                              typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
-                             const typename Prec<PREC>::chunk_t* __restrict__ W,
-                             const float* __restrict__ bias, uint32_t (&msk)[mask_words<PREC, H>()],
-                             int lane) {
+                             const char* __restrict__ W, const char* __restrict__ Wnext,
+                             int next_bytes, const float* __restrict__ bias,
+                             uint32_t (&msk)[mask_words<PREC, H>()],
+                             typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW, int& buf,
+                             int lane, int w, int z) {
   using T = Prec<PREC>;
+  using chunk_t = typename T::chunk_t;
   constexpr int NB = T::NB, VPC = T::VPC;
   constexpr int OB = H / 32;
-  constexpr int CPO = 16 / VPC;  // chunks per output block
+  constexpr int CPO = 16 / VPC;  // chunks per output block and point block
+  constexpr int NEPI = NB * CPO;  // epilogue chunks per output block
+  constexpr int OBP = panel_obs<KC, H>();
+  constexpr int PB = panel_bytes<KC, H>();
+  constexpr int D = 3;  // LDS prefetch distance (K-steps)
+  constexpr int MFMA_PER_STEP = (PREC == PREC_BF16 ? 1 : 4) * NB;
+  static_assert(OB % OBP == 0, "panels must tile the output blocks");
   const int hf = lane >> 5;
   if (EPI == EPI_RELU_BIAS)
 #pragma unroll
     for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
+  f32x16 accp[NB];
 #pragma unroll
   for (int ob = 0; ob < OB; ++ob) {
-    f32x16 acc[NB];
+    if (ob % OBP == 0) {
+      wait_dma();
+      __syncthreads();
+      char* nxt = sW + (buf ^ 1) * PANEL_BYTES;
+      if (ob + OBP < OB) dma_panel(W + (ob / OBP + 1) * PB, nxt, PB, w, lane);
+      else if (Wnext) dma_panel(Wnext, nxt, next_bytes, w, lane);
+      if (ob == 0 && stash) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
-#pragma unroll
-    for (int c = 0; c < KC; ++c) {
-      const typename T::chunk_t wa = W[(ob * KC + c) * 64 + lane];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) T::mma(acc[nb], wa, x[nb][c]);
+          for (int c = 0; c < KC; ++c) stash[(nb * KC + c) * 64 + lane] = x[nb][c];
+      }
     }
-    // rows of this lane: 32 ob + 8 q + 4 hf + (0..3)
-    float bq[16];
+    const chunk_t* __restrict__ Wp =
+        (const chunk_t*)(sW + buf * PANEL_BYTES) + (ob % OBP) * KC * 64;
+    f32x16 acc[NB];
     if (EPI == EPI_RELU_BIAS) {
+      float bq[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 b4 = *(const float4*)(bias + 32 * ob + 8 * q + 4 * hf);
+        const float4 b4 = *(const float4*)(bias + z + 32 * ob + 8 * q + 4 * hf);
         bq[4 * q + 0] = b4.x; bq[4 * q + 1] = b4.y; bq[4 * q + 2] = b4.z; bq[4 * q + 3] = b4.w;
       }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[nb][r] = bq[r];
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[nb][r] = 0.f;
     }
+    chunk_t a[D + 1];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      float v[16];
-      uint32_t bits = 0;
-      const int mw = (nb * OB + ob) >> 1, sh = 16 * ((nb * OB + ob) & 1);
-      if (EPI == EPI_RELU_BIAS) {
+    for (int c = 0; c < D && c < KC; ++c) a[c] = Wp[c * 64 + lane];
+    __builtin_amdgcn_sched_group_barrier(0x100, D < KC ? D : KC, 0);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const float z = acc[nb][r] + bq[r];
-          v[r] = z > 0.f ? z : 0.f;
-          bits |= (z > 0.f ? 1u : 0u) << r;
-        }
-        msk[mw] |= bits << sh;
-      } else {
-        bits = msk[mw] >> sh;
+    for (int c = 0; c < KC; ++c) {
+      if (c + D < KC) a[(c + D) % (D + 1)] = Wp[(c + D) * 64 + lane];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = ((bits >> r) & 1u) ? acc[nb][r] : 0.f;
+      for (int nb = 0; nb < NB; ++nb) T::mma(acc[nb], a[c % (D + 1)], x[nb][c]);
+      __builtin_amdgcn_sched_group_barrier(0x008, MFMA_PER_STEP, 0);
+      if (c + D < KC) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      if (ob > 0) {
+        // epilogue chunks of block ob-1 assigned to this step
+#pragma unroll
+        for (int k = 0; k < NEPI; ++k)
+          if ((k * KC) / NEPI == c) epi_chunk<PREC, H, EPI>(accp, ob - 1, k, y, msk);
       }
-#pragma unroll
-      for (int k = 0; k < CPO; ++k) y[nb][ob * CPO + k] = T::from_f32(&v[k * VPC]);
     }
-  }
-}
-
-template <int PREC, int CH>
-__device__ inline void stash_store(typename Prec<PREC>::chunk_t* __restrict__ dst,
-                                   const typename Prec<PREC>::chunk_t (&x)[CH], int lane) {
 #pragma unroll
-  for (int c = 0; c < CH; ++c) dst[c * 64 + lane] = x[c];
+    for (int nb = 0; nb < NB; ++nb) accp[nb] = acc[nb];
+    if ((ob + 1) % OBP == 0) buf ^= 1;
+  }
+#pragma unroll
+  for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk);
 }
 
 template <int PREC, int IN, int H, int MODE>
@@ -335,11 +426,12 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   constexpr int CI = chunks<PREC>(IN), CHh = chunks<PREC>(H);
   constexpr int TILE = WAVES_PER_WG * NB * 32;
   constexpr int C = IN / 2;
-  constexpr int OB = H / 32;
   constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
   constexpr int MSK_LAYERS = (MODE == MODE_BWD) ? MAX_LAYERS - 1 : 1;
+  constexpr int PB_IN = panel_bytes<CI, H>(), PB_H = panel_bytes<CHh, H>();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hf = lane >> 5, pl = lane & 31;
 
+  __shared__ __align__(16) char sW[2 * PANEL_BYTES];
   __shared__ float4 sB[C];
   __shared__ float sval[TILE];
   __shared__ int32_t srid[TILE];
@@ -347,19 +439,31 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
 
+  const char* __restrict__ Wpk = (const char*)a.Wpk;
+  const char* __restrict__ WTpk = (const char*)a.WTpk;
+  const int64_t P = a.off[a.R];
+  const int64_t n_tiles = (P + TILE - 1) / TILE;
+  const int64_t t_end = a.tile_end < n_tiles ? a.tile_end : n_tiles;
+  const float bo = a.params[a.bo_off];
+  const int L = a.L;
+  auto Wl = [&](int l) { return Wpk + a.wpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
+  auto WTl = [&](int l) { return WTpk + a.wtpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
+
+  int buf = 0;
+  const int64_t t0 = a.tile_begin + blockIdx.x;
+  if (t0 < t_end) dma_panel(Wl(0), sW, PB_IN, w, lane);
   for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
   if (MODE == MODE_BWD)
     for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
   __syncthreads();
 
-  const chunk_t* __restrict__ Wpk = (const chunk_t*)a.Wpk;
-  const chunk_t* __restrict__ WTpk = (const chunk_t*)a.WTpk;
-  const int64_t P = a.off[a.R];
-  const int64_t n_tiles = (P + TILE - 1) / TILE;
-  const int64_t t_end = a.tile_end < n_tiles ? a.tile_end : n_tiles;
-  const float bo = a.params[a.bo_off];
-
-  for (int64_t t = a.tile_begin + blockIdx.x; t < t_end; t += gridDim.x) {
+  for (int64_t t = t0; t < t_end; t += gridDim.x) {
+    const bool more = t + gridDim.x < t_end;
+    // a zero the compiler cannot see through: keeps the per-lane loads of B
+    // rows, biases and w_o inside the tile loop instead of hoisting (and
+    // spilling) hundreds of loop-invariant values
+    int z = 0;
+    asm volatile("" : "+v"(z));
     int rid[NB];
     float wgt[NB];
     chunk_t x0[NB][CI];
@@ -391,7 +495,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
         float cv[VPC], sv[VPC];
 #pragma unroll
         for (int e = 0; e < VPC; ++e) {
-          const float4 b = sB[feat(VPC * c + e, hf)];
+          const float4 b = sB[z + feat(VPC * c + e, hf)];
           const float u = b.x * rt + b.y * rz + b.z * ry + b.w * rx;
           const float f = u - rintf(u);
           sincos_rev<PREC>(f, &sv[e], &cv[e]);
@@ -402,37 +506,36 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
     }
     const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
     uint32_t* msk_w = &smsk[w][0][0][0];
+    auto hstash = [&](int l, int ch) -> chunk_t* {
+      return MODE == MODE_BWD ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
+    };
+    // what follows the last forward layer in the panel sequence
+    const char* after_fwd = (MODE == MODE_BWD && L > 1) ? WTl(L - 1) : (more ? Wl(0) : nullptr);
+    const int after_fwd_bytes = (MODE == MODE_BWD && L > 1) ? PB_H : PB_IN;
     // ---- hidden layers (Appendix B item 3)
     chunk_t y[NB][CHh];
-    if (MODE == MODE_BWD) {
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        stash_store<PREC, CI>((chunk_t*)a.stash + a.h_base[0] + (blk0 + nb) * (CI * 64), x0[nb],
-                              lane);
-    }
     {
       uint32_t mk[MSK_PER_LAYER];
-      layer<PREC, CI, H, EPI_RELU_BIAS>(x0, y, Wpk, a.bias, mk, lane);
-      if (MODE == MODE_BWD && a.L > 1)
+      const char* nx = L > 1 ? Wl(1) : after_fwd;
+      const int nxb = L > 1 ? PB_H : after_fwd_bytes;
+      layer<PREC, CI, H, EPI_RELU_BIAS>(x0, y, Wl(0), nx, nxb, a.bias, mk, hstash(0, CI), sW, buf,
+                                        lane, w, z);
+      if (MODE == MODE_BWD && L > 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
-    for (int l = 1; l < a.L; ++l) {
+    for (int l = 1; l < L; ++l) {
       chunk_t xh[NB][CHh];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int c = 0; c < CHh; ++c) xh[nb][c] = y[nb][c];
-      if (MODE == MODE_BWD) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          stash_store<PREC, CHh>((chunk_t*)a.stash + a.h_base[l] + (blk0 + nb) * (CHh * 64),
-                                 xh[nb], lane);
-      }
       uint32_t mk[MSK_PER_LAYER];
-      layer<PREC, CHh, H, EPI_RELU_BIAS>(xh, y, Wpk + a.wpk_off[l] / VPC, a.bias + l * H, mk,
-                                         lane);
-      if (MODE == MODE_BWD && l < a.L - 1)
+      const char* nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
+      const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
+      layer<PREC, CHh, H, EPI_RELU_BIAS>(xh, y, Wl(l), nx, nxb, a.bias + l * H, mk,
+                                         hstash(l, CHh), sW, buf, lane, w, z);
+      if (MODE == MODE_BWD && l < L - 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
@@ -440,7 +543,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
     float zo[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
-    const float* wop = a.wo_perm + hf * (H / 2);
+    const float* wop = a.wo_perm + z + hf * (H / 2);
 #pragma unroll
     for (int c = 0; c < CHh; ++c) {
 #pragma unroll
@@ -497,36 +600,37 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
         dob[nb] = rid[nb] >= 0 ? a.gup[rid[nb]] * wgt[nb] * dMdz : 0.f;
       }
       // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
-      // Halving butterfly over the 32 lanes of each half: after 5 steps lane
-      // pl holds the sums of slots 4 pl .. 4 pl + 3.
+      // Halving butterfly over the 32 lanes of each half, in two passes over
+      // the slots: after 5 steps lane pl holds the sums of KF consecutive slots.
       {
-        constexpr int K = H / 2;
-        float v[K];
+        constexpr int K = (H / 2) < 64 ? H / 2 : 64;  // slots per pass (a multiple of 32)
 #pragma unroll
-        for (int c = 0; c < CHh; ++c)
+        for (int pass = 0; pass < (H / 2) / K; ++pass) {
+          float v[K];
 #pragma unroll
-          for (int e = 0; e < VPC; ++e) {
+          for (int i = 0; i < K; ++i) {
+            const int rho = pass * K + i;
             float s = 0.f;
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][c], e);
-            v[VPC * c + e] = s;
+            for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][rho / VPC], rho % VPC);
+            v[i] = s;
           }
 #pragma unroll
-        for (int st = 0; st < 5; ++st) {
-          const int o = 16 >> st;
-          const int half = K >> (st + 1);
-          const bool up = (pl & o) != 0;
+          for (int st = 0; st < 5; ++st) {
+            const int o = 16 >> st;
+            const int half = K >> (st + 1);
+            const bool up = (pl & o) != 0;
 #pragma unroll
-          for (int i = 0; i < half; ++i) {
-            const float send = up ? v[i] : v[i + half];
-            const float keep = up ? v[i + half] : v[i];
-            v[i] = keep + __shfl_xor(send, o);
+            for (int i = 0; i < half; ++i) {
+              const float send = up ? v[i] : v[i + half];
+              const float keep = up ? v[i + half] : v[i];
+              v[i] = keep + __shfl_xor(send, o);
+            }
           }
+          constexpr int KF = K / 32;
+#pragma unroll
+          for (int i = 0; i < KF; ++i) sdwo[w][feat(pass * K + KF * pl + i, hf)] += v[i];
         }
-        constexpr int KF = K / 32;
-        const int f0 = feat(KF * pl, hf);
-#pragma unroll
-        for (int i = 0; i < KF; ++i) sdwo[w][f0 + i] += v[i];
         float sb = 0.f;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) sb += dob[nb];
@@ -549,28 +653,38 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
           d[nb][c] = T::from_f32(v);
         }
       }
-      const int L = a.L;
+      auto dstash = [&](int l) { return (chunk_t*)a.stash + a.d_base[l] + blk0 * (CHh * 64); };
+      if (L == 1) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        stash_store<PREC, CHh>((chunk_t*)a.stash + a.d_base[L - 1] + (blk0 + nb) * (CHh * 64), d[nb],
-                               lane);
-      // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int c = 0; c < CHh; ++c) dstash(0)[(nb * CHh + c) * 64 + lane] = d[nb][c];
+      }
+      // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
+      // call stores its input delta_l for the weight gradient
       for (int l = L - 1; l >= 1; --l) {
         uint32_t mk[MSK_PER_LAYER];
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
         chunk_t dn[NB][CHh];
-        layer<PREC, CHh, H, EPI_MASK>(d, dn, WTpk + a.wtpk_off[l] / VPC, nullptr, mk, lane);
+        const char* nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : nullptr);
+        const int nxb = l > 1 ? PB_H : PB_IN;
+        layer<PREC, CHh, H, EPI_MASK>(d, dn, WTl(l), nx, nxb, nullptr, mk, dstash(l), sW, buf,
+                                      lane, w, z);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int c = 0; c < CHh; ++c) d[nb][c] = dn[nb][c];
-          stash_store<PREC, CHh>((chunk_t*)a.stash + a.d_base[l - 1] + (blk0 + nb) * (CHh * 64),
-                                 d[nb], lane);
+        if (l == 1) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c) dstash(0)[(nb * CHh + c) * 64 + lane] = d[nb][c];
         }
       }
     }
   }
+  wait_dma();
   if (MODE == MODE_BWD) {
     __syncthreads();
     for (int f = threadIdx.x; f <= H; f += blockDim.x) {

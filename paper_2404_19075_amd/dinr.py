@@ -55,7 +55,9 @@ class Adam(C.Structure):
 
 
 EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
-           "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status"]
+           "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
+           "dinr_profile_enable", "dinr_profile_read"]
+PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD = 0, 1, 2
 
 _lib = None
 
@@ -86,6 +88,10 @@ def load(path: str = LIB_PATH):
     L.dinr_step.restype = i32
     L.dinr_step_status.argtypes = [vp, vp]
     L.dinr_step_status.restype = i32
+    L.dinr_profile_enable.argtypes = [vp, i32]
+    L.dinr_profile_enable.restype = i32
+    L.dinr_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.dinr_profile_read.restype = i32
     _lib = L
     return L
 
@@ -197,6 +203,16 @@ class Context:
 
     def step_status(self) -> int:
         return int(self._lib.dinr_step_status(self._h, _stream()))
+
+    def profile(self, enable: bool = True):
+        self._check(self._lib.dinr_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, kind: int):
+        """(total milliseconds, launches) of one kernel class since the last read."""
+        t = C.c_double()
+        n = C.c_int64()
+        self._check(self._lib.dinr_profile_read(self._h, kind, C.byref(t), C.byref(n)))
+        return t.value, n.value
 
 
 def project_function():
