@@ -72,9 +72,10 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     ms = e0.elapsed_time(e1) / steps
     kern = {}
     for kind, kname in [(dinr.PROF_MLP_FWD, "mlp_fwd"), (dinr.PROF_MLP_BWD, "mlp_bwd"),
-                        (dinr.PROF_WGRAD, "wgrad")]:
+                        (dinr.PROF_MLP_FUSED, "mlp_fused"), (dinr.PROF_WGRAD, "wgrad")]:
         t, n = ctx.profile_read(kind)
-        kern[kname] = dict(total_ms=t, launches=n, ms_per_step=t / steps)
+        if n:
+            kern[kname] = dict(total_ms=t, launches=n, ms_per_step=t / steps)
     status = ctx.step_status()
     ctx.close()
     del P, idx, meas, grad, proj, m, v, P0
@@ -151,7 +152,7 @@ def main():
     # the forward, one backward launch per stash chunk, one wgrad launch per
     # layer and chunk)
     alg = {"mlp_fwd": f_fwd * P_pts, "mlp_bwd": (f_dx + 2 * shapes[-1][1]) * P_pts,
-           "wgrad": f_dw * P_pts}
+           "mlp_fused": (f_fwd + f_dx + 2 * shapes[-1][1]) * P_pts, "wgrad": f_dw * P_pts}
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     ach = alg[dom] / (kern[dom]["ms_per_step"] * 1e-3)
     roof = dict(bound="mfma", kernel=dom, achieved=ach / 1e12, peak=PEAK["bf16"] / 1e12,

@@ -90,7 +90,11 @@ typedef struct {
   int32_t act;
   int32_t out_act;
   int32_t precision;
-  int32_t reserved0, reserved1;
+  int32_t recompute;  /* 1: training steps always run the forward kernel and then a
+                         backward kernel that recomputes the activations; 0: when
+                         every tile of points holds whole rays (fixed n dividing the
+                         tile) the step runs forward, loss and adjoint in one pass */
+  int32_t reserved;
   double mu0;
 } dinr_mlp;
 
@@ -181,7 +185,8 @@ enum {
   DINR_PROF_MLP_FWD = 0,  /* fused forward: coordinates, encoding, MLP, ray-sum */
   DINR_PROF_MLP_BWD = 1,  /* recomputed forward and adjoint chain, operand stash */
   DINR_PROF_WGRAD = 2,    /* weight-gradient reduction over the stash */
-  DINR_PROF_KINDS = 3
+  DINR_PROF_MLP_FUSED = 3, /* one-pass forward, ray-sum, loss terms and adjoint chain */
+  DINR_PROF_KINDS = 4
 };
 int dinr_profile_enable(dinr_ctx* ctx, int enable);
 int dinr_profile_read(dinr_ctx* ctx, int kind, double* total_ms, int64_t* launches);

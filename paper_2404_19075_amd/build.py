@@ -15,7 +15,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fno-fast-math", "-ffp-contract=fast",
+    "-fno-fast-math", "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -125,6 +125,7 @@ struct Plan {
   int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS];
   float* wpart = nullptr;
   float* opart = nullptr;
+  double* lpart = nullptr;
   double* gn_part = nullptr;
   int grid_mlp = 0;
 };
@@ -200,6 +201,7 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
     A.ok = true;
     const int64_t n_chunks = (pts_pad + chunk - 1) / chunk;
     p->opart = A.take<float>((size_t)n_chunks * p->grid_mlp * (c->H + 1));
+    p->lpart = A.take<double>((size_t)n_chunks * p->grid_mlp);
     p->stash = A.take<char>((size_t)chunk * per_point * esize(c->prec));
     if (A.ok) {
       p->chunk_points = chunk;
@@ -268,10 +270,13 @@ static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
   return DINR_OK;
 }
 
-// Adjoint given the upstream gradient in gup (rays, offsets and packed
-// weights already in place).
+// Adjoint (rays, offsets and packed weights already in place).  mode
+// MODE_BWD: upstream gradient given in gup, forward recomputed per tile.
+// MODE_FUSED: forward, ray-sums, residuals against meas and the adjoint in
+// one pass; proj receives the predictions and lpart the residual sums.
 static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, const float* gup,
-                           float* grad, double* gnorm_out, hipStream_t st) {
+                           float* grad, double* gnorm_out, hipStream_t st, int mode = MODE_BWD,
+                           const float* meas = nullptr, float* proj = nullptr) {
   const int prec = c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32;
   const int64_t tiles_per_chunk = p.chunk_points / c->tile;
   for (int64_t ch = 0; ch < p.n_chunks; ++ch) {
@@ -279,6 +284,9 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
     a.tile_begin = ch * tiles_per_chunk;
     a.tile_end = std::min<int64_t>((ch + 1) * tiles_per_chunk, p.n_tiles_max);
     a.gup = gup;
+    a.meas = meas;
+    a.proj = proj;
+    a.lpart = p.lpart + ch * (int64_t)p.grid_mlp;
     a.stash = p.stash;
     for (int l = 0; l < c->L; ++l) {
       a.h_base[l] = p.h_base[l];
@@ -286,8 +294,8 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
     }
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
     {
-      ProfScope ps(c, DINR_PROF_MLP_BWD, st);
-      HIPCHK(c, launch_mlp(prec, c->IN, c->H, MODE_BWD, a, p.grid_mlp, st));
+      ProfScope ps(c, mode == MODE_FUSED ? DINR_PROF_MLP_FUSED : DINR_PROF_MLP_BWD, st);
+      HIPCHK(c, launch_mlp(prec, c->IN, c->H, mode, a, p.grid_mlp, st));
     }
     for (int l = 0; l < c->L; ++l) {
       WgArgs w{};
@@ -326,6 +334,9 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
   r.np = c->np;
   r.grad = grad;
   r.gn_part = p.gn_part;
+  if (mode == MODE_FUSED)
+    HIPCHK(c, launch_loss_fused(p.rays, meas, p.R, p.lpart, p.n_chunks * p.grid_mlp, proj,
+                                c->d_scal, st));
   HIPCHK(c, launch_reduce(r, c->d_scal + 1, gnorm_out, st));
   return DINR_OK;
 }
@@ -595,12 +606,25 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   float* proj = proj_out ? proj_out : p.proj;
-  rc = enqueue_forward(c, p, params, idx, proj, nullptr, st);
-  if (rc) return rc;
-  HIPCHK(c, launch_loss(proj, meas, R, p.gup, c->d_scal, st));
-  if (loss) HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
-  rc = enqueue_adjoint(c, p, params, p.gup, grad, gnorm, st);
-  if (rc) return rc;
+  const bool fused = !c->mlp.recompute && c->samp.mode == 0 && c->tile % c->samp.n == 0;
+  if (fused) {
+    HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
+                          p.tr0, st));
+    HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk,
+                          p.WTpk, p.bias, p.wo, st));
+    rc = enqueue_adjoint(c, p, params, nullptr, grad, gnorm, st, MODE_FUSED, meas, proj);
+    if (rc) return rc;
+    if (loss)
+      HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    rc = enqueue_forward(c, p, params, idx, proj, nullptr, st);
+    if (rc) return rc;
+    HIPCHK(c, launch_loss(proj, meas, R, p.gup, c->d_scal, st));
+    if (loss)
+      HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
+    rc = enqueue_adjoint(c, p, params, p.gup, grad, gnorm, st);
+    if (rc) return rc;
+  }
   if (adam) {
     const float c1 = (float)(1.0 - std::pow((double)adam->beta1, (double)adam->step));
     const float c2 = (float)(1.0 - std::pow((double)adam->beta2, (double)adam->step));

@@ -10,7 +10,10 @@
 namespace dinr {
 
 constexpr int MAX_LAYERS = 10;
-enum { MODE_FWD = 0, MODE_BWD = 1 };
+// FWD: forward + ray-sum.  BWD: recomputed forward + adjoint from a given
+// upstream gradient.  FUSED: forward, in-tile ray-sum, loss terms and the
+// adjoint in one pass (tiles must hold whole rays).
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_FUSED = 2 };
 
 struct GeomDev {
   int kind, rows, cols, n_views, fov_kind;
@@ -60,6 +63,9 @@ struct MlpArgs {
   int64_t h_base[MAX_LAYERS];  // chunk (16 B) offsets of h_l blocks
   int64_t d_base[MAX_LAYERS];  // chunk offsets of delta_l blocks
   float* opart;              // [grid][H+1] output-layer gradient partials
+  // fused mode
+  const float* meas;         // [R] measured projections
+  double* lpart;             // [grid] partial sums of squared residuals
 };
 
 struct WgArgs {
@@ -101,6 +107,8 @@ hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int t
                         const float* part, float* proj, hipStream_t st);
 hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
                        hipStream_t st);
+hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, const double* lpart,
+                             int64_t n_lpart, float* proj, double* loss, hipStream_t st);
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const RedArgs& a, double* gnorm_ws, double* gnorm_out, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,

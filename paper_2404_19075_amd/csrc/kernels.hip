@@ -427,7 +427,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   constexpr int TILE = WAVES_PER_WG * NB * 32;
   constexpr int C = IN / 2;
   constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
-  constexpr int MSK_LAYERS = (MODE == MODE_BWD) ? MAX_LAYERS - 1 : 1;
+  constexpr int MSK_LAYERS = (MODE != MODE_FWD) ? MAX_LAYERS - 1 : 1;
   constexpr int PB_IN = panel_bytes<CI, H>(), PB_H = panel_bytes<CHh, H>();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hf = lane >> 5, pl = lane & 31;
 
@@ -435,6 +435,8 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   __shared__ float4 sB[C];
   __shared__ float sval[TILE];
   __shared__ int32_t srid[TILE];
+  __shared__ float sg[TILE];  // fused mode: upstream gradient of the tile's rays
+  __shared__ double sloss[256];
   __shared__ float sdwo[WAVES_PER_WG][H + 1];
   // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
@@ -446,6 +448,10 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   const int64_t t_end = a.tile_end < n_tiles ? a.tile_end : n_tiles;
   const float bo = a.params[a.bo_off];
   const int L = a.L;
+  constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED;
+  constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
+  double lossacc = 0.0;
+  const float g_scale = 2.0f / (float)a.R;
   auto Wl = [&](int l) { return Wpk + a.wpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
   auto WTl = [&](int l) { return WTpk + a.wtpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
 
@@ -453,7 +459,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   const int64_t t0 = a.tile_begin + blockIdx.x;
   if (t0 < t_end) dma_panel(Wl(0), sW, PB_IN, w, lane);
   for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
-  if (MODE == MODE_BWD)
+  if (MODE != MODE_FWD)
     for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
   __syncthreads();
 
@@ -465,6 +471,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
     int z = 0;
     asm volatile("" : "+v"(z));
     int rid[NB];
+    int poff[NB];  // first point of the point's ray, relative to the tile
     float wgt[NB];
     chunk_t x0[NB][CI];
     // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
@@ -473,6 +480,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
       float rt = 0.f, rz = 0.f, ry = 0.f, rx = 0.f;
       rid[nb] = -1;
+      poff[nb] = 0;
       wgt[nb] = 0.f;
       if (p < P) {
         int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
@@ -488,6 +496,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
         ry = rr.py + s * rr.dy;
         rx = rr.px + s * rr.dx;
         rid[nb] = (int)lo;
+        poff[nb] = (int)(a.off[lo] - t * TILE);
         wgt[nb] = rr.wgt;
       }
 #pragma unroll
@@ -507,11 +516,11 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
     const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
     uint32_t* msk_w = &smsk[w][0][0][0];
     auto hstash = [&](int l, int ch) -> chunk_t* {
-      return MODE == MODE_BWD ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
+      return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
     };
     // what follows the last forward layer in the panel sequence
-    const char* after_fwd = (MODE == MODE_BWD && L > 1) ? WTl(L - 1) : (more ? Wl(0) : nullptr);
-    const int after_fwd_bytes = (MODE == MODE_BWD && L > 1) ? PB_H : PB_IN;
+    const char* after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : nullptr);
+    const int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
     // ---- hidden layers (Appendix B item 3)
     chunk_t y[NB][CHh];
     {
@@ -520,7 +529,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       const int nxb = L > 1 ? PB_H : after_fwd_bytes;
       layer<PREC, CI, H, EPI_RELU_BIAS>(x0, y, Wl(0), nx, nxb, a.bias, mk, hstash(0, CI), sW, buf,
                                         lane, w, z);
-      if (MODE == MODE_BWD && L > 1)
+      if (BWD_PART && L > 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
       layer<PREC, CHh, H, EPI_RELU_BIAS>(xh, y, Wl(l), nx, nxb, a.bias + l * H, mk,
                                          hstash(l, CHh), sW, buf, lane, w, z);
-      if (MODE == MODE_BWD && l < L - 1)
+      if (BWD_PART && l < L - 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
@@ -556,7 +565,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) zo[nb] += __shfl_xor(zo[nb], 32) + bo;
 
-    if (MODE == MODE_FWD) {
+    if (FWD_PART) {
       // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -584,20 +593,36 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
           const int64_t o1 = a.off[r + 1];
           const int64_t tb = t * TILE;
           const float sum = sval[tp];
-          if (o0 < tb) a.part[2 * t + 0] = sum;
-          else if (o1 > tb + TILE) a.part[2 * t + 1] = sum;
-          else a.proj[r] = a.rays[r].wgt * sum;
+          if (MODE == MODE_FUSED) {
+            // whole ray in this tile: prediction, residual, upstream gradient
+            // rounded product (no contraction into the residual), as in the
+            // forward kernel, so both passes produce the same residuals
+            const float pbar = __fmul_rn(a.rays[r].wgt, sum);
+            a.proj[r] = pbar;
+            const float e = pbar - a.meas[r];
+            lossacc += (double)e * (double)e;
+            sg[o0 - tb] = g_scale * e;
+          } else if (o0 < tb) {
+            a.part[2 * t + 0] = sum;
+          } else if (o1 > tb + TILE) {
+            a.part[2 * t + 1] = sum;
+          } else {
+            a.proj[r] = __fmul_rn(a.rays[r].wgt, sum);
+          }
         }
       }
       __syncthreads();
-    } else {
+    }
+    if (BWD_PART) {
       // ---- adjoint (Eq. (8)): dL/dM = g_r mu0 l_r / n_r, through the output map
       float dob[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const float z = zo[nb];
         const float dMdz = a.out_act ? 1.f / (1.f + expf(-z)) : 1.f;
-        dob[nb] = rid[nb] >= 0 ? a.gup[rid[nb]] * wgt[nb] * dMdz : 0.f;
+        float gr = 0.f;
+        if (rid[nb] >= 0) gr = MODE == MODE_FUSED ? sg[poff[nb]] : a.gup[rid[nb]];
+        dob[nb] = gr * wgt[nb] * dMdz;
       }
       // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
       // Halving butterfly over the 32 lanes of each half, in two passes over
@@ -685,13 +710,22 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
     }
   }
   wait_dma();
-  if (MODE == MODE_BWD) {
+  if (BWD_PART) {
     __syncthreads();
     for (int f = threadIdx.x; f <= H; f += blockDim.x) {
       float s = 0.f;
       for (int ww = 0; ww < WAVES_PER_WG; ++ww) s += sdwo[ww][f];
       a.opart[(int64_t)blockIdx.x * (H + 1) + f] = s;
     }
+  }
+  if (MODE == MODE_FUSED) {
+    sloss[threadIdx.x] = lossacc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sloss[threadIdx.x] += sloss[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.lpart[blockIdx.x] = sloss[0];
   }
 }
 
@@ -715,7 +749,7 @@ __global__ void k_fixup(const RayRec* __restrict__ rays, const int64_t* __restri
     comp = (tt - s) - y;
     s = tt;
   }
-  proj[r] = rr.wgt * s;
+  proj[r] = __fmul_rn(rr.wgt, s);
 }
 
 // Loss (Eq. (5)) in FP64 and the upstream gradient g_r = 2 (pbar_r - p_r) / R.
@@ -741,38 +775,75 @@ __global__ __launch_bounds__(1024) void k_loss(const float* __restrict__ proj,
   if (t == 0) *loss = s[0] / (double)R;
 }
 
+// Loss of the fused pass: the MLP kernel's per-workgroup sums of squared
+// residuals, plus rays that hold no samples (prediction 0, so the residual
+// is the measurement) and rays with an invalid index (NaN).  One workgroup,
+// fixed order.
+__global__ __launch_bounds__(1024) void k_loss_fused(const RayRec* __restrict__ rays,
+                                                      const float* __restrict__ meas, int64_t R,
+                                                      const double* __restrict__ lpart,
+                                                      int64_t n_lpart, float* __restrict__ proj,
+                                                      double* __restrict__ loss) {
+  __shared__ double s[1024];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t k = t; k < n_lpart; k += 1024) acc += lpart[k];
+  for (int64_t r = t; r < R; r += 1024) {
+    const RayRec rr = rays[r];
+    if (rr.flags & 1) {
+      proj[r] = __builtin_nanf("");
+      acc += (double)__builtin_nanf("");
+    } else if (rr.n == 0) {
+      proj[r] = 0.f;
+      acc += (double)meas[r] * (double)meas[r];
+    }
+  }
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) s[t] += s[t + o];
+    __syncthreads();
+  }
+  if (t == 0) *loss = s[0] / (double)R;
+}
+
 // ------------------------------------------------------------ dW
 
 // dW_l[o][i] = sum_p delta_l[p][o] h_{l-1}[p][i]  (and db_l = sum_p delta_l[p])
 // over the stash blocks of one split.  The stash holds blocks of 32 points in
-// the register layout of k_mlp; each block is transposed through LDS into
-// [feature][point] rows so that both matrix-core operands are read as 16-byte
-// runs of consecutive points (K = points).
+// the register layout of k_mlp; each iteration transposes NBLK blocks through
+// LDS into [feature][point] rows so that both matrix-core operands are read
+// as 16-byte runs of consecutive points (K = points).  The stash chunks of the
+// next iteration are loaded into registers while the current one is reduced.
 template <int PREC, int FI, int H>
 __global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
   using T = Prec<PREC>;
   using E = typename T::elem_t;
   using chunk_t = typename T::chunk_t;
   constexpr int VPC = T::VPC;
+  constexpr int NBLK = PREC == PREC_BF16 ? 2 : 1;  // 32-point blocks per iteration
+  constexpr int BP = 32 * NBLK;                     // points per iteration
   constexpr int CHd = chunks<PREC>(H), CHi = chunks<PREC>(FI);
-  constexpr int ROW = 32 + 16 / (int)sizeof(E);  // padded row (elements)
+  constexpr int ROW = BP + 16 / (int)sizeof(E);  // padded row (elements)
   constexpr int RB = H / 32, CB = FI / 32, NT = RB * CB;
   constexpr int NW = 8;
   constexpr int TPW = (NT + NW - 1) / NW;
+  constexpr int QD = NBLK * CHd * 64 / 512, QH = NBLK * CHi * 64 / 512;  // chunks per thread
+  static_assert(QD * 512 == NBLK * CHd * 64 && QH * 512 == NBLK * CHi * 64, "chunk split");
   __shared__ __align__(16) E sD[H * ROW];
   __shared__ __align__(16) E sH[FI * ROW];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hf = lane >> 5;
-  const int s = a.layer;
 
   const int64_t P = a.off[a.R];
   const int64_t n_tiles = (P + a.tile - 1) / a.tile;
   int64_t pend = n_tiles * a.tile;
   if (pend > a.chunk_p1) pend = a.chunk_p1;
-  const int64_t nblk = (pend - a.chunk_p0) / 32;
-  const int64_t b0 = (int64_t)blockIdx.x * a.kb;
-  int64_t b1 = b0 + a.kb;
-  if (b1 > nblk) b1 = nblk;
-  if (b0 >= b1) return;
+  const int64_t nblk = (pend - a.chunk_p0) / 32;  // valid 32-point blocks of the chunk
+  const int64_t it0 = (int64_t)blockIdx.x * (a.kb / NBLK);
+  int64_t it1 = it0 + a.kb / NBLK;
+  const int64_t nit = (nblk + NBLK - 1) / NBLK;
+  if (it1 > nit) it1 = nit;
+  if (it0 >= it1) return;
 
   f32x16 acc[TPW];
 #pragma unroll
@@ -783,26 +854,47 @@ __global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
 
   const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
   const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
+  chunk_t cd[QD], ch[QH];
+  auto load = [&](int64_t it, chunk_t (&d)[QD], chunk_t (&h)[QH]) {
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = tid + 512 * k;
+      const bool ok = it * NBLK + q / (CHd * 64) < nblk;
+      d[k] = ok ? Dst[it * (NBLK * CHd * 64) + q] : T::zero();
+    }
+#pragma unroll
+    for (int k = 0; k < QH; ++k) {
+      const int q = tid + 512 * k;
+      const bool ok = it * NBLK + q / (CHi * 64) < nblk;
+      h[k] = ok ? Hst[it * (NBLK * CHi * 64) + q] : T::zero();
+    }
+  };
+  load(it0, cd, ch);
 
-  for (int64_t b = b0; b < b1; ++b) {
+  for (int64_t it = it0; it < it1; ++it) {
     __syncthreads();
-    for (int q = tid; q < CHd * 64; q += 512) {
-      const chunk_t v = Dst[b * (CHd * 64) + q];
-      const int c = q >> 6, l = q & 63;
 #pragma unroll
-      for (int e = 0; e < VPC; ++e) sD[feat(VPC * c + e, l >> 5) * ROW + (l & 31)] = (E)T::get(v, e);
-    }
-    for (int q = tid; q < CHi * 64; q += 512) {
-      const chunk_t v = Hst[b * (CHi * 64) + q];
-      const int c = q >> 6, l = q & 63;
+    for (int k = 0; k < QD; ++k) {
+      const int q = tid + 512 * k;
+      const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
+      const int p = bl * 32 + (l & 31);
 #pragma unroll
-      for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + (l & 31)] = (E)T::get(v, e);
+      for (int e = 0; e < VPC; ++e) sD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
     }
+#pragma unroll
+    for (int k = 0; k < QH; ++k) {
+      const int q = tid + 512 * k;
+      const int bl = q / (CHi * 64), c = (q / 64) % CHi, l = q & 63;
+      const int p = bl * 32 + (l & 31);
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
+    }
+    if (it + 1 < it1) load(it + 1, cd, ch);
     __syncthreads();
     if (tid < H) {
       float sb = 0.f;
 #pragma unroll
-      for (int p = 0; p < 32; ++p) sb += (float)sD[tid * ROW + p];
+      for (int p = 0; p < BP; ++p) sb += (float)sD[tid * ROW + p];
       dbacc += sb;
     }
 #pragma unroll
@@ -814,7 +906,7 @@ __global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
         const E* rbp = sH + (32 * cb + (lane & 31)) * ROW;
         if (PREC == PREC_BF16) {
 #pragma unroll
-          for (int st = 0; st < 2; ++st) {
+          for (int st = 0; st < BP / 16; ++st) {
             const chunk_t av = *(const chunk_t*)(ra + 16 * st + 8 * hf);
             const chunk_t bv = *(const chunk_t*)(rbp + 16 * st + 8 * hf);
             T::mma(acc[k], av, bv);
@@ -969,8 +1061,10 @@ template <int PREC, int IN, int H>
 static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st) {
   if (mode == MODE_FWD)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD>), dim3(grid), dim3(256), 0, st, a);
-  else
+  else if (mode == MODE_BWD)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED>), dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -996,6 +1090,13 @@ hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int t
 hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, st, proj, meas, R, g, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, const double* lpart,
+                             int64_t n_lpart, float* proj, double* loss, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss_fused, dim3(1), dim3(1024), 0, st, rays, meas, R, lpart, n_lpart, proj,
+                     loss);
   return hipGetLastError();
 }
 

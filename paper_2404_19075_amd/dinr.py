@@ -40,7 +40,7 @@ class Geometry(C.Structure):
 class MLP(C.Structure):
     _fields_ = [("n_freq", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
                 ("act", C.c_int32), ("out_act", C.c_int32), ("precision", C.c_int32),
-                ("reserved0", C.c_int32), ("reserved1", C.c_int32), ("mu0", C.c_double)]
+                ("recompute", C.c_int32), ("reserved", C.c_int32), ("mu0", C.c_double)]
 
 
 class Sampling(C.Structure):
@@ -57,7 +57,7 @@ class Adam(C.Structure):
 EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
            "dinr_profile_enable", "dinr_profile_read"]
-PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD = 0, 1, 2
+PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
 
 _lib = None
 
@@ -125,13 +125,14 @@ class Context:
     """One libdinr context: geometry, network shape, sampling, B, workspace."""
 
     def __init__(self, geom, mlp_spec, sampling, B: np.ndarray, precision: int = FP32,
-                 workspace_bytes: int = 1 << 30):
+                 workspace_bytes: int = 1 << 30, recompute: bool = False):
         L = load()
         keep: list = []
         g = _geometry(geom, keep)
         m = MLP()
         m.n_freq, m.width, m.depth = mlp_spec.n_freq, mlp_spec.width, mlp_spec.depth
         m.act, m.out_act, m.precision, m.mu0 = mlp_spec.act, mlp_spec.out_act, precision, mlp_spec.mu0
+        m.recompute = 1 if recompute else 0
         s = Sampling()
         s.mode, s.n, s.n_min, s.n_max, s.h = (sampling.mode, sampling.n, sampling.n_min,
                                               sampling.n_max, sampling.h)

@@ -56,7 +56,8 @@ def device_inputs(batch: S.Batch, dev="cuda"):
             torch.tensor(batch.meas, device=dev))
 
 
-def make_ctx(w: S.Workload, B: np.ndarray, precision: int, ws_bytes: int = 2 << 30):
+def make_ctx(w: S.Workload, B: np.ndarray, precision: int, ws_bytes: int = 2 << 30,
+             recompute: bool = False):
     from paper_2404_19075_amd import dinr
     return dinr.Context(w.geom, w.mlp, w.sampling, B, precision=precision,
-                        workspace_bytes=ws_bytes)
+                        workspace_bytes=ws_bytes, recompute=recompute)

@@ -39,8 +39,8 @@ def run_forward(w, batch, prec):
     return out
 
 
-def run_step(w, batch, prec, adam=None):
-    ctx = make_ctx(w, batch.B, prec)
+def run_step(w, batch, prec, adam=None, recompute=False):
+    ctx = make_ctx(w, batch.B, prec, recompute=recompute)
     P = torch.tensor(batch.params, device="cuda")
     idx = torch.tensor(batch.idx, device="cuda")
     meas = torch.tensor(batch.meas, device="cuda")
@@ -257,3 +257,19 @@ def test_autograd_function_matches_adjoint():
     assert rel(P.grad.cpu().numpy(), grad.cpu().numpy()) <= 1e-5
     assert abs(loss.item() - loss2.item()) <= 1e-6 * loss2.item()
     ctx.close()
+
+
+@pytest.mark.parametrize("name,R", [("c0", 1024), ("c1", 160)])
+def test_fused_pass_matches_recompute_pass(name, R):
+    """The one-pass step (forward, loss and adjoint per tile of whole rays)
+    and the two-pass step (forward kernel, loss kernel, backward kernel that
+    recomputes the activations) evaluate the same arithmetic per point."""
+    w = small_workload(name, R)
+    b = S.make_batch(w)
+    o1 = run_step(w, b, BF16)
+    o2 = run_step(w, b, BF16, recompute=True)
+    log(f"  {name}: proj equal {np.array_equal(o1['proj'], o2['proj'])}, "
+        f"grad rel diff {rel(o1['grad'], o2['grad']):.3e}, loss {o1['loss']:.9e} {o2['loss']:.9e}")
+    assert np.array_equal(o1["proj"], o2["proj"])
+    assert rel(o1["grad"], o2["grad"]) <= 1e-6
+    assert abs(o1["loss"] - o2["loss"]) <= 1e-12 * o2["loss"]
