@@ -77,10 +77,93 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
         if n:
             kern[kname] = dict(total_ms=t, launches=n, ms_per_step=t / steps)
     status = ctx.step_status()
+    trained = P.cpu().numpy()
     ctx.close()
     del P, idx, meas, grad, proj, m, v, P0
     torch.cuda.empty_cache()
-    return ms, kern, ref, status
+    return ms, kern, ref, status, trained
+
+
+def serving(batch, params_np, duration_s=4.0, rates=(0.25, 0.5, 0.9), seed=7):
+    """Continuously batched queries of the trained field (BF16): a 50/50 mix of
+    n x n slices (n in 64..512) at random (z, t) and parallel-beam
+    reprojections (n in 128..512, 256 samples per ray) at random (theta, t),
+    arriving as a Poisson stream.  Returns capacity and p50/p99 latency per
+    rate."""
+    import torch
+    from paper_2404_19075_amd import dinr
+    w = batch.workload
+    ctx = dinr.Context(w.geom, w.mlp, w.sampling, batch.B, precision=dinr.BF16,
+                       workspace_bytes=64 << 20)
+    P = torch.tensor(params_np, device="cuda")
+    srv = dinr.Server(ctx, P, mem_budget=1 << 30, max_active=64)
+    rng = np.random.default_rng(seed)
+    pool = [torch.empty(512 * 512, device="cuda") for _ in range(64)]
+    busy = [None] * len(pool)
+
+    def draw():
+        if rng.random() < 0.5:
+            return (dinr.QUERY_SLICE, int(rng.choice([64, 128, 256, 512])),
+                    float(rng.uniform(-1, 1)), float(rng.uniform(0, 1)), 0)
+        return (dinr.QUERY_REPROJECTION, int(rng.choice([128, 256, 384, 512])),
+                float(rng.uniform(0, 2 * np.pi)), float(rng.uniform(0, 1)), 256)
+
+    def free_slot():
+        # an output buffer whose last request has completed (tickets are
+        # released by whoever collects their latency)
+        while True:
+            for k, tk in enumerate(busy):
+                if tk is None or srv.poll(tk)[0]:
+                    busy[k] = None
+                    return k
+            time.sleep(0.0002)
+
+    # capacity: a closed batch of mixed requests submitted at once
+    reqs = [draw() for _ in range(24)]
+    t0 = time.perf_counter()
+    tks = []
+    for r in reqs:
+        k = free_slot()
+        busy[k] = srv.submit(r[0], r[1], r[2], r[3], pool[k], samples_per_ray=r[4])
+        tks.append(busy[k])
+    for tk in tks:
+        srv.wait(tk)
+    cap = len(reqs) / (time.perf_counter() - t0)
+    for tk in tks:
+        srv.release(tk)
+    busy = [None] * len(pool)
+    log(f"serving capacity {cap:.2f} req/s")
+    out = dict(capacity_req_per_s=cap, mix="50% slices n=64..512, 50% reprojections n=128..512 "
+               "x 256 samples", rates=[])
+    for frac in rates:
+        rate = frac * cap
+        n_req = max(int(rate * duration_s), 8)
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrivals = np.cumsum(gaps)
+        lat = []
+        pending = []
+        start = time.perf_counter()
+        for a in arrivals:
+            while time.perf_counter() - start < a:
+                time.sleep(0.0002)
+            r = draw()
+            k = free_slot()
+            busy[k] = srv.submit(r[0], r[1], r[2], r[3], pool[k], samples_per_ray=r[4])
+            pending.append(busy[k])
+        for tk in pending:
+            srv.wait(tk)
+            lat.append(srv.poll(tk)[1])
+            srv.release(tk)
+        busy = [None] * len(pool)
+        span = time.perf_counter() - start
+        lat = np.array(lat)
+        row = dict(rate_req_per_s=rate, requests=len(lat), p50_ms=float(np.percentile(lat, 50)),
+                   p99_ms=float(np.percentile(lat, 99)), throughput_req_per_s=len(lat) / span)
+        log(f"serving rate {rate:.2f}/s: {json.dumps(row)}")
+        out["rates"].append(row)
+    srv.close()
+    ctx.close()
+    return out
 
 
 def cpu_baseline(batch, n_rays=192):
@@ -107,6 +190,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workspace-gb", type=float, default=120.0)
+    ap.add_argument("--no-serving", action="store_true", help="skip the query-serving run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share of the batch; this build has no multi-GPU "
@@ -124,13 +208,13 @@ def main():
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s: R={len(batch.idx)} points={P_pts}")
     ws = int(args.workspace_gb * (1 << 30))
 
-    ms_bf16, kern, ref_bf16, status = run_workload("c2", dinr.BF16, batch, args.steps,
-                                                   args.warmup, ws)
+    ms_bf16, kern, ref_bf16, status, trained = run_workload("c2", dinr.BF16, batch, args.steps,
+                                                            args.warmup, ws)
     log(f"bf16 step {ms_bf16:.3f} ms  kernels {json.dumps(kern)}  status {status}")
     fp32 = None
     if not args.no_fp32:
-        ms_fp32, kern32, ref_fp32, _ = run_workload("c1", dinr.FP32, batch, max(2, args.steps // 4),
-                                                    1, ws)
+        ms_fp32, kern32, ref_fp32, _, _ = run_workload("c1", dinr.FP32, batch,
+                                                       max(2, args.steps // 4), 1, ws)
         log(f"fp32 step {ms_fp32:.3f} ms  kernels {json.dumps(kern32)}")
 
         def rel(a, b):
@@ -161,9 +245,11 @@ def main():
                                  alg_tflops=alg[k] / (kern[k]["ms_per_step"] * 1e-3) / 1e12)
                          for k in kern},
                 step_frac=(f_all * P_pts / (ms_bf16 * 1e-3)) / PEAK["bf16"])
+    serve = None if args.no_serving else serving(batch, trained)
     cpu = None if args.no_cpu else cpu_baseline(batch)
     out = {
-        "metric": "ray-samples/s fwd+bwd (one training step incl. Adam), BF16 matrix cores",
+        "metric": "ray-samples/s fwd+bwd (one training step incl. Adam), BF16 matrix cores; "
+                  "p50/p99 query ms",
         "value": P_pts / (ms_bf16 * 1e-3),
         "unit": "ray-samples/s",
         "n_gpus": 1,
@@ -182,6 +268,9 @@ def main():
                    "rays": len(batch.idx), "samples_per_ray": w.sampling.n,
                    "ray_samples": P_pts, "flop_per_sample": f_all},
         "fp32": fp32,
+        "serving": serve,
+        "p50_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p50_ms"],
+        "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "status": status,

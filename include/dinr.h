@@ -174,6 +174,68 @@ int dinr_step(dinr_ctx* ctx, float* params_d, const int64_t* proj_idx_d, int64_t
  * requested, was then skipped), else DINR_OK. */
 int dinr_step_status(dinr_ctx* ctx, void* stream);
 
+/* ------------------------------------------------------------------ queries
+ * Queries of a trained field (Sec. IV: the network is evaluated on a grid at a
+ * view's time, or re-projected): a server keeps the packed weights resident
+ * and batches requests continuously on its own stream.
+ *  - DINR_QUERY_SLICE: n x n image of mu0 M at height z = z_or_theta (world
+ *    units) and time t; pixel (i, j) is at normalised (x, y) =
+ *    (-1 + (2j+1)/n, -1 + (2i+1)/n) of the FOV; out[i*n + j].
+ *  - DINR_QUERY_REPROJECTION: predicted projections (Eq. (1)) of an n x n
+ *    detector with the scanner's geometry kind and detector extent (pitch
+ *    scaled by rows/n and cols/n), rotated by theta = z_or_theta, at time t,
+ *    with samples_per_ray equi-spaced samples per ray (a divisor of 256 for
+ *    BF16 contexts, of 128 for FP32); out[row*n + col], 0 for rays that
+ *    miss the FOV. */
+enum { DINR_QUERY_SLICE = 0, DINR_QUERY_REPROJECTION = 1 };
+
+typedef struct {
+  int32_t kind;
+  int32_t n;
+  double z_or_theta;
+  double t;
+  int32_t samples_per_ray;
+  int32_t reserved;
+} dinr_request;
+
+typedef struct dinr_server dinr_server;
+
+/* Create a query server for `ctx` with the parameters in params_d (device
+ * FP32 [n_params]; read at creation to pack the weights and for b_o, so it
+ * must stay valid and unchanged while the server lives).  mem_budget bounds
+ * the output bytes (4 n^2 per request) of the requests admitted at once;
+ * max_active bounds their number.  Starts the scheduler thread.  The server
+ * uses its own stream; the context must outlive it and must not be used
+ * concurrently for training. */
+int dinr_server_create(dinr_ctx* ctx, const float* params_d, size_t mem_budget,
+                       int32_t max_active, dinr_server** out);
+
+/* Stops admitting, finishes the requests already admitted, drops queued
+ * ones, frees the server. */
+int dinr_server_destroy(dinr_server* srv);
+
+/* Submit a request (any thread; never blocks).  out_d: caller-owned device
+ * FP32 [n*n], written by the server; valid once dinr_poll reports done.
+ * Requests queue in arrival order and are admitted when their output bytes fit
+ * in the budget and a slot is free.  DINR_ENOMEM if the request alone exceeds
+ * the budget, DINR_EINVAL for a malformed request, DINR_EBUSY once stopped. */
+int dinr_query(dinr_server* srv, const dinr_request* req, float* out_d, uint64_t* ticket);
+
+/* done = 1 when the request's output is complete; latency_ms (nullable) gets
+ * submit-to-completion time in milliseconds (host clock), or -1. */
+int dinr_poll(dinr_server* srv, uint64_t ticket, int32_t* done, double* latency_ms);
+
+/* Block until the request completes (DINR_OK) or the server stops. */
+int dinr_query_wait(dinr_server* srv, uint64_t ticket);
+
+/* Forget a completed request's record. */
+int dinr_query_release(dinr_server* srv, uint64_t ticket);
+
+/* Counters: kernel launches, tiles run, bytes of admitted outputs, queued
+ * and admitted requests (all nullable). */
+int dinr_server_stats(dinr_server* srv, int64_t* launches, int64_t* tiles, size_t* bytes_in_use,
+                      int32_t* queued, int32_t* admitted);
+
 /* Kernel timing (a tracing aid, off by default).  While enabled, every
  * launch of the kernels below is bracketed by a pair of HIP events recorded
  * on the call's stream (at most 4096 launches per kind between reads).

@@ -29,7 +29,6 @@ typedef __attribute__((__vector_size__(8 * sizeof(float)))) float f32x8;
 enum { PREC_F32 = 0, PREC_BF16 = 1 };
 
 constexpr int WAVE = 64;
-constexpr int WAVES_PER_WG = 4;
 
 __host__ __device__ constexpr int feat(int rho, int hf) {
   return 32 * (rho / 16) + 8 * ((rho % 16) / 4) + 4 * hf + (rho % 4);
@@ -42,8 +41,9 @@ template <>
 struct Prec<PREC_BF16> {
   using chunk_t = bf16x8;
   using elem_t = __bf16;
-  static constexpr int VPC = 8;   // values per chunk per lane
-  static constexpr int NB = 2;    // 32-point blocks per wave
+  static constexpr int VPC = 8;    // values per chunk per lane
+  static constexpr int NB = 1;     // 32-point blocks per wave
+  static constexpr int WAVES = 8;  // waves per workgroup (two per SIMD)
   __device__ static inline void mma(f32x16& acc, const chunk_t& a, const chunk_t& b) {
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
   }
@@ -56,6 +56,10 @@ struct Prec<PREC_BF16> {
     f32x8 t = {0, 0, 0, 0, 0, 0, 0, 0};
     return __builtin_convertvector(t, bf16x8);
   }
+  // streaming store (non-temporal: does not displace reused data in L2)
+  __device__ static inline void store_nt(chunk_t* p, const chunk_t& v) {
+    __builtin_nontemporal_store(v, p);
+  }
 };
 
 template <>
@@ -64,6 +68,7 @@ struct Prec<PREC_F32> {
   using elem_t = float;
   static constexpr int VPC = 4;
   static constexpr int NB = 1;
+  static constexpr int WAVES = 4;
   __device__ static inline void mma(f32x16& acc, const chunk_t& a, const chunk_t& b) {
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, acc, 0, 0, 0);
@@ -77,6 +82,11 @@ struct Prec<PREC_F32> {
     return e == 0 ? c.x : e == 1 ? c.y : e == 2 ? c.z : c.w;
   }
   __device__ static inline chunk_t zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ static inline void store_nt(chunk_t* p, const chunk_t& v) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (f4*)p);
+  }
 };
 
 // chunks per lane for F features

@@ -13,7 +13,25 @@ constexpr int MAX_LAYERS = 10;
 // FWD: forward + ray-sum.  BWD: recomputed forward + adjoint from a given
 // upstream gradient.  FUSED: forward, in-tile ray-sum, loss terms and the
 // adjoint in one pass (tiles must hold whole rays).
-enum { MODE_FWD = 0, MODE_BWD = 1, MODE_FUSED = 2 };
+// QUERY: points of queued requests (slices or reprojection rays) listed in a
+// tile table; outputs mu0 M per point or ray-sums per ray.
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_FUSED = 2, MODE_QUERY = 3 };
+
+// One admitted query (device copy).  kind 0: n x n slice of mu0 M at height
+// zn and time tn (normalised), pixel (i, j) at normalised (x, y) =
+// (-1 + (2j+1)/n, -1 + (2i+1)/n).  kind 1: reprojection on an n x n detector
+// covering the scanner's detector extent, view angle (cth, sth), time tn,
+// `samples` equi-spaced samples per ray (a divisor of the tile size).
+struct QueryDesc {
+  int kind, n, samples, pad;
+  float zn, tn, cth, sth;
+  float* out;
+};
+
+struct QueryTile {
+  int slot;  // descriptor index
+  int tile;  // tile index within the query
+};
 
 struct GeomDev {
   int kind, rows, cols, n_views, fov_kind;
@@ -66,6 +84,11 @@ struct MlpArgs {
   // fused mode
   const float* meas;         // [R] measured projections
   double* lpart;             // [grid] partial sums of squared residuals
+  // query mode
+  const QueryDesc* qdesc;
+  const QueryTile* qtiles;
+  int64_t n_qtiles;
+  GeomDev geom;
 };
 
 struct WgArgs {
@@ -103,6 +126,7 @@ hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, v
                        float* bias, float* wo, hipStream_t st);
 hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int grid,
                       hipStream_t st);
+hipError_t launch_query(int prec, int in, int h, const MlpArgs& a, int grid, hipStream_t st);
 hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int tile,
                         const float* part, float* proj, hipStream_t st);
 hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,

@@ -26,32 +26,11 @@ namespace dinr {
 // in FP32.  Object rotation by theta equals rotating the source-detector pair
 // by -theta about z.  Coordinates are stored already normalised to [-1,1]
 // (Appendix B item 1).
-__global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
-                       RayRec* __restrict__ rays, int32_t* __restrict__ nray,
-                       int32_t* __restrict__ n_out) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  RayRec rec;
-  const int64_t i = idx[r];
-  const int64_t N = (int64_t)g.rows * g.cols;
-  if (i < 0 || i >= N * g.n_views) {
-    rec.px = rec.py = rec.pz = rec.s_in = 0.f;
-    rec.dx = rec.dy = rec.dz = rec.dl = 0.f;
-    rec.tn = 0.f;
-    rec.wgt = 0.f;
-    rec.n = 0;
-    rec.flags = 1;
-    rays[r] = rec;
-    nray[r] = 0;
-    if (n_out) n_out[r] = 0;
-    return;
-  }
-  const int m = (int)(i / N);
-  const int64_t pix = i - (int64_t)m * N;
-  const int row = (int)(pix / g.cols);
-  const int col = (int)(pix - (int64_t)row * g.cols);
-  const float u = ((float)col - 0.5f * (float)(g.cols - 1)) * g.pitch_u + g.off_u;
-  const float v = ((float)row - 0.5f * (float)(g.rows - 1)) * g.pitch_v + g.off_v;
+// Ray through detector position (u, v) of a view rotated by theta (c = cos,
+// s = sin), clipped to the FOV, with its sample count (fixed n, or
+// clamp(ceil(l/h)) when samp_mode = 1).
+__device__ inline RayRec make_ray(const GeomDev& g, float u, float v, float c, float s, float tn,
+                                  int samp_mode, int samp_n) {
   float p0x, p0y, p0z, d0x, d0y, d0z;
   if (g.kind == 0) {
     p0x = 0.f; p0y = u; p0z = v;
@@ -63,7 +42,6 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     p0y = g.sod * d0x * d0y;
     p0z = g.sod * d0x * d0z;
   }
-  const float c = g.cth[m], s = g.sth[m];
   const float px = c * p0x + s * p0y, py = -s * p0x + c * p0y, pz = p0z;
   const float dx = c * d0x + s * d0y, dy = -s * d0x + c * d0y, dz = d0z;
   // FOV clip
@@ -72,12 +50,12 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
   if (g.fov_kind == 0) {
     const float o[3] = {px, py, pz}, d[3] = {dx, dy, dz};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float b0 = g.fov[2 * a], b1 = g.fov[2 * a + 1];
-      if (d[a] == 0.f) {
-        if (o[a] < b0 || o[a] > b1) miss = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      const float b0 = g.fov[2 * ax], b1 = g.fov[2 * ax + 1];
+      if (d[ax] == 0.f) {
+        if (o[ax] < b0 || o[ax] > b1) miss = true;
       } else {
-        float ta = (b0 - o[a]) / d[a], tb = (b1 - o[a]) / d[a];
+        float ta = (b0 - o[ax]) / d[ax], tb = (b1 - o[ax]) / d[ax];
         lo = fmaxf(lo, fminf(ta, tb));
         hi = fminf(hi, fmaxf(ta, tb));
       }
@@ -107,17 +85,18 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
       hi = fminf(hi, fmaxf(ta, tb));
     }
   }
-  float len = (!miss && hi > lo) ? hi - lo : 0.f;
+  const float len = (!miss && hi > lo) ? hi - lo : 0.f;
   int n = 0;
   if (len > 0.f) {
-    if (g.samp_mode == 0) {
-      n = g.samp_n;
+    if (samp_mode == 0) {
+      n = samp_n;
     } else {
       float q = ceilf(len / g.samp_h);
       q = fminf(fmaxf(q, (float)g.samp_min), (float)g.samp_max);
       n = (int)q;
     }
   }
+  RayRec rec;
   rec.px = px * g.sc[0] + g.oc[0];
   rec.py = py * g.sc[1] + g.oc[1];
   rec.pz = pz * g.sc[2] + g.oc[2];
@@ -126,13 +105,43 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
   rec.dz = dz * g.sc[2];
   rec.s_in = (n > 0) ? lo : 0.f;
   rec.dl = (n > 0) ? len / (float)n : 0.f;
-  rec.tn = g.tnorm[m];
+  rec.tn = tn;
   rec.wgt = (n > 0) ? g.mu0 * len / (float)n : 0.f;
   rec.n = n;
   rec.flags = 0;
+  return rec;
+}
+
+__global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
+                       RayRec* __restrict__ rays, int32_t* __restrict__ nray,
+                       int32_t* __restrict__ n_out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t i = idx[r];
+  const int64_t N = (int64_t)g.rows * g.cols;
+  if (i < 0 || i >= N * g.n_views) {
+    RayRec rec;
+    rec.px = rec.py = rec.pz = rec.s_in = 0.f;
+    rec.dx = rec.dy = rec.dz = rec.dl = 0.f;
+    rec.tn = 0.f;
+    rec.wgt = 0.f;
+    rec.n = 0;
+    rec.flags = 1;
+    rays[r] = rec;
+    nray[r] = 0;
+    if (n_out) n_out[r] = 0;
+    return;
+  }
+  const int m = (int)(i / N);
+  const int64_t pix = i - (int64_t)m * N;
+  const int row = (int)(pix / g.cols);
+  const int col = (int)(pix - (int64_t)row * g.cols);
+  const float u = ((float)col - 0.5f * (float)(g.cols - 1)) * g.pitch_u + g.off_u;
+  const float v = ((float)row - 0.5f * (float)(g.rows - 1)) * g.pitch_v + g.off_v;
+  const RayRec rec = make_ray(g, u, v, g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode, g.samp_n);
   rays[r] = rec;
-  nray[r] = n;
-  if (n_out) n_out[r] = n;
+  nray[r] = rec.n;
+  if (n_out) n_out[r] = rec.n;
 }
 
 // Exclusive scan of n[R] into off[R+1] (one workgroup; R is at most a few
@@ -273,11 +282,13 @@ __host__ __device__ constexpr int panel_bytes() { return panel_obs<KC, H>() * KC
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// bytes: a multiple of 4 KB (256 threads x 16 B).  Wave w copies the 1 KB
-// blocks w, w+4, ...; the LDS destination of one instruction is wave-uniform.
+// bytes: a multiple of 1 KB times the wave count.  Wave w of nw copies the
+// 1 KB blocks w, w+nw, ...; the LDS destination of one instruction is
+// wave-uniform.
+template <int NW>
 __device__ inline void dma_panel(const char* __restrict__ src, char* dst, int bytes, int w,
                                  int lane) {
-  for (int off = w * 1024; off < bytes; off += 4096)
+  for (int off = w * 1024; off < bytes; off += NW * 1024)
     __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 16), (lds_void*)(dst + off),
                                      16, 0, 0);
 }
@@ -297,10 +308,22 @@ __host__ __device__ constexpr int mask_words() { return Prec<PREC>::NB * (H / 32
 
 // Epilogue of one 16-byte chunk of an output block: ReLU (recording mask
 // bits) or the stored mask applied, then conversion to the operand type.
+// 0 - x as an opaque VALU op: keeps "(-r) >> 31" a subtract and a shift
+// instead of being rewritten into a compare into a lane mask and a select.
+__device__ inline uint32_t neg_u32(uint32_t x) {
+  uint32_t r;
+  asm("v_sub_u32 %0, 0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 template <int PREC, int H, int EPI>
 __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, int k,
                                  typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
                                  uint32_t (&msk)[mask_words<PREC, H>()]) {
+  // Pure integer VALU on the bit patterns (no compares into lane masks):
+  // ReLU is max_i32(bits, 0) (negative floats are negative integers); its
+  // mask bit is the sign of -relu (1 iff z > 0); masking ANDs the value with
+  // the sign-extended bit.
   using T = Prec<PREC>;
   constexpr int VPC = T::VPC, CPO = 16 / VPC, OB = H / 32;
   const int nb = k / CPO, kk = k % CPO;
@@ -311,15 +334,19 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
     uint32_t bits = 0;
 #pragma unroll
     for (int e = 0; e < VPC; ++e) {
-      const float zv = acc[nb][kk * VPC + e];
-      v[e] = zv > 0.f ? zv : 0.f;
-      bits |= (zv > 0.f ? 1u : 0u) << e;
+      const int zi = __float_as_int(acc[nb][kk * VPC + e]);
+      const int r = zi > 0 ? zi : 0;  // v_max_i32
+      v[e] = __int_as_float(r);
+      bits |= (neg_u32((uint32_t)r) >> 31) << e;
     }
     msk[mw] |= bits << sh;
   } else {
     const uint32_t bits = msk[mw] >> sh;
 #pragma unroll
-    for (int e = 0; e < VPC; ++e) v[e] = ((bits >> e) & 1u) ? acc[nb][kk * VPC + e] : 0.f;
+    for (int e = 0; e < VPC; ++e) {
+      const int keep = -(int)((bits >> e) & 1u);  // 0 or all ones
+      v[e] = __int_as_float(__float_as_int(acc[nb][kk * VPC + e]) & keep);
+    }
   }
   y[nb][ob * CPO + kk] = T::from_f32(v);
 }
@@ -363,13 +390,14 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
       wait_dma();
       __syncthreads();
       char* nxt = sW + (buf ^ 1) * PANEL_BYTES;
-      if (ob + OBP < OB) dma_panel(W + (ob / OBP + 1) * PB, nxt, PB, w, lane);
-      else if (Wnext) dma_panel(Wnext, nxt, next_bytes, w, lane);
+      if (ob + OBP < OB) dma_panel<T::WAVES>(W + (ob / OBP + 1) * PB, nxt, PB, w, lane);
+      else if (Wnext) dma_panel<T::WAVES>(Wnext, nxt, next_bytes, w, lane);
       if (ob == 0 && stash) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int c = 0; c < KC; ++c) stash[(nb * KC + c) * 64 + lane] = x[nb][c];
+          for (int c = 0; c < KC; ++c)
+            T::store_nt(&stash[(nb * KC + c) * 64 + lane], x[nb][c]);
       }
     }
     const chunk_t* __restrict__ Wp =
@@ -419,11 +447,12 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 }
 
 template <int PREC, int IN, int H, int MODE>
-__global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
+__global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   using T = Prec<PREC>;
   using chunk_t = typename T::chunk_t;
   constexpr int NB = T::NB, VPC = T::VPC;
   constexpr int CI = chunks<PREC>(IN), CHh = chunks<PREC>(H);
+  constexpr int WAVES_PER_WG = T::WAVES;
   constexpr int TILE = WAVES_PER_WG * NB * 32;
   constexpr int C = IN / 2;
   constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
@@ -436,19 +465,21 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   __shared__ float sval[TILE];
   __shared__ int32_t srid[TILE];
   __shared__ float sg[TILE];  // fused mode: upstream gradient of the tile's rays
-  __shared__ double sloss[256];
+  __shared__ float swgt[TILE];  // query mode: weight mu0 l / n of each point's ray
+  __shared__ double sloss[WAVES_PER_WG * 64];
   __shared__ float sdwo[WAVES_PER_WG][H + 1];
   // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
 
   const char* __restrict__ Wpk = (const char*)a.Wpk;
   const char* __restrict__ WTpk = (const char*)a.WTpk;
-  const int64_t P = a.off[a.R];
-  const int64_t n_tiles = (P + TILE - 1) / TILE;
-  const int64_t t_end = a.tile_end < n_tiles ? a.tile_end : n_tiles;
+  constexpr bool QUERY = MODE == MODE_QUERY;
+  const int64_t P = QUERY ? 0 : a.off[a.R];
+  const int64_t n_tiles = QUERY ? a.n_qtiles : (P + TILE - 1) / TILE;
+  const int64_t t_end = QUERY ? n_tiles : (a.tile_end < n_tiles ? a.tile_end : n_tiles);
   const float bo = a.params[a.bo_off];
   const int L = a.L;
-  constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED;
+  constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED || MODE == MODE_QUERY;
   constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
   double lossacc = 0.0;
   const float g_scale = 2.0f / (float)a.R;
@@ -456,8 +487,8 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   auto WTl = [&](int l) { return WTpk + a.wtpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
 
   int buf = 0;
-  const int64_t t0 = a.tile_begin + blockIdx.x;
-  if (t0 < t_end) dma_panel(Wl(0), sW, PB_IN, w, lane);
+  const int64_t t0 = (QUERY ? 0 : a.tile_begin) + blockIdx.x;
+  if (t0 < t_end) dma_panel<WAVES_PER_WG>(Wl(0), sW, PB_IN, w, lane);
   for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
   if (MODE != MODE_FWD)
     for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
@@ -482,7 +513,45 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       rid[nb] = -1;
       poff[nb] = 0;
       wgt[nb] = 0.f;
-      if (p < P) {
+      if (QUERY) {
+        const QueryTile qt = a.qtiles[t];
+        const QueryDesc q = a.qdesc[qt.slot];
+        const int tp = w * (NB * 32) + nb * 32 + pl;
+        rt = q.tn;
+        if (q.kind == 0) {
+          const int64_t pq = (int64_t)qt.tile * TILE + tp;
+          if (pq < (int64_t)q.n * q.n) {
+            const int i = (int)(pq / q.n), j = (int)(pq - (int64_t)i * q.n);
+            rz = q.zn;
+            ry = -1.f + (2.f * i + 1.f) / (float)q.n;
+            rx = -1.f + (2.f * j + 1.f) / (float)q.n;
+            rid[nb] = (int)pq;
+          }
+        } else {
+          const int S = q.samples;
+          const int64_t ray = (int64_t)qt.tile * (TILE / S) + tp / S;
+          const int j = tp % S;
+          if (ray < (int64_t)q.n * q.n) {
+            const int row = (int)(ray / q.n), col = (int)(ray - (int64_t)row * q.n);
+            const GeomDev& g = a.geom;
+            const float pu = g.pitch_u * (float)g.cols / (float)q.n;
+            const float pv = g.pitch_v * (float)g.rows / (float)q.n;
+            const float u = ((float)col - 0.5f * (float)(q.n - 1)) * pu + g.off_u;
+            const float v = ((float)row - 0.5f * (float)(q.n - 1)) * pv + g.off_v;
+            const RayRec rr = make_ray(g, u, v, q.cth, q.sth, q.tn, 0, S);
+            if (rr.n > 0) {
+              const float s = rr.s_in + ((float)j + 0.5f) * rr.dl;
+              rz = rr.pz + s * rr.dz;
+              ry = rr.py + s * rr.dy;
+              rx = rr.px + s * rr.dx;
+              rid[nb] = (int)(tp / S);
+              wgt[nb] = rr.wgt;
+            } else if (j == 0 && hf == 0) {
+              q.out[ray] = 0.f;  // the ray misses the field of view
+            }
+          }
+        }
+      } else if (p < P) {
         int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
         if (hi > a.R - 1) hi = a.R - 1;
         while (lo < hi) {
@@ -533,20 +602,29 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
-    for (int l = 1; l < L; ++l) {
-      chunk_t xh[NB][CHh];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int c = 0; c < CHh; ++c) xh[nb][c] = y[nb][c];
+    // hidden layers 2..L, two per iteration with the roles of y and z swapped
+    // so that no activation array is copied between layers
+    auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
       uint32_t mk[MSK_PER_LAYER];
       const char* nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
       const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
-      layer<PREC, CHh, H, EPI_RELU_BIAS>(xh, y, Wl(l), nx, nxb, a.bias + l * H, mk,
+      layer<PREC, CHh, H, EPI_RELU_BIAS>(in, out, Wl(l), nx, nxb, a.bias + l * H, mk,
                                          hstash(l, CHh), sW, buf, lane, w, z);
       if (BWD_PART && l < L - 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+    };
+    for (int l = 1; l < L; l += 2) {
+      chunk_t t2[NB][CHh];
+      hidden(l, y, t2);
+      if (l + 1 < L) {
+        hidden(l + 1, t2, y);
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int c = 0; c < CHh; ++c) y[nb][c] = t2[nb][c];
+      }
     }
     // ---- output unit (Appendix B item 4) with the configured output map
     float zo[NB];
@@ -567,14 +645,22 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
 
     if (FWD_PART) {
       // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
+      const QueryDesc* qd = QUERY ? &a.qdesc[a.qtiles[t].slot] : nullptr;
+      const bool slice = QUERY && qd->kind == 0;
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const float z = zo[nb];
         const float M = a.out_act ? fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) : z;
         if (hf == 0) {
           const int tp = w * (NB * 32) + nb * 32 + pl;
-          sval[tp] = rid[nb] >= 0 ? M : 0.f;
-          srid[tp] = rid[nb];
+          if (slice) {
+            if (rid[nb] >= 0) qd->out[rid[nb]] = a.geom.mu0 * M;  // mu0 M: attenuation
+            srid[tp] = -1;
+          } else {
+            sval[tp] = rid[nb] >= 0 ? M : 0.f;
+            srid[tp] = rid[nb];
+            if (QUERY) swgt[tp] = wgt[nb];
+          }
         }
       }
       __syncthreads();
@@ -589,11 +675,16 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       if (tp < TILE) {
         const int r = srid[tp];
         if (r >= 0 && (tp == TILE - 1 || srid[tp + 1] != r)) {
-          const int64_t o0 = a.off[r];
-          const int64_t o1 = a.off[r + 1];
+          const int64_t o0 = QUERY ? 0 : a.off[r];
+          const int64_t o1 = QUERY ? 0 : a.off[r + 1];
           const int64_t tb = t * TILE;
           const float sum = sval[tp];
-          if (MODE == MODE_FUSED) {
+          if (QUERY) {
+            // whole rays per tile: ray rid of this tile
+            const QueryTile qt = a.qtiles[t];
+            const int64_t ray = (int64_t)qt.tile * (TILE / qd->samples) + r;
+            qd->out[ray] = __fmul_rn(swgt[tp], sum);
+          } else if (MODE == MODE_FUSED) {
             // whole ray in this tile: prediction, residual, upstream gradient
             // rounded product (no contraction into the residual), as in the
             // forward kernel, so both passes produce the same residuals
@@ -628,7 +719,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
       // Halving butterfly over the 32 lanes of each half, in two passes over
       // the slots: after 5 steps lane pl holds the sums of KF consecutive slots.
       {
-        constexpr int K = (H / 2) < 64 ? H / 2 : 64;  // slots per pass (a multiple of 32)
+        constexpr int K = 32;  // slots per pass (the butterfly needs a multiple of 32)
 #pragma unroll
         for (int pass = 0; pass < (H / 2) / K; ++pass) {
           float v[K];
@@ -674,7 +765,12 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
         for (int nb = 0; nb < NB; ++nb) {
           float v[VPC];
 #pragma unroll
-          for (int e = 0; e < VPC; ++e) v[e] = T::get(y[nb][c], e) > 0.f ? wv[e] * dob[nb] : 0.f;
+          for (int e = 0; e < VPC; ++e) {
+            // h_L >= 0 (ReLU output): h > 0 iff its bit pattern is non-zero
+            const int hb = __float_as_int(T::get(y[nb][c], e));
+            const int keep = (int)neg_u32((uint32_t)hb) >> 31;  // 0 or all ones
+            v[e] = __int_as_float(__float_as_int(wv[e] * dob[nb]) & keep);
+          }
           d[nb][c] = T::from_f32(v);
         }
       }
@@ -683,29 +779,39 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int c = 0; c < CHh; ++c) dstash(0)[(nb * CHh + c) * 64 + lane] = d[nb][c];
+          for (int c = 0; c < CHh; ++c)
+            T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
       }
       // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
-      // call stores its input delta_l for the weight gradient
-      for (int l = L - 1; l >= 1; --l) {
+      // call stores its input delta_l for the weight gradient.  Two layers per
+      // iteration with swapped roles, as in the forward.
+      auto adj = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
         uint32_t mk[MSK_PER_LAYER];
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
-        chunk_t dn[NB][CHh];
         const char* nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : nullptr);
         const int nxb = l > 1 ? PB_H : PB_IN;
-        layer<PREC, CHh, H, EPI_MASK>(d, dn, WTl(l), nx, nxb, nullptr, mk, dstash(l), sW, buf,
+        layer<PREC, CHh, H, EPI_MASK>(in, out, WTl(l), nx, nxb, nullptr, mk, dstash(l), sW, buf,
                                       lane, w, z);
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int c = 0; c < CHh; ++c) d[nb][c] = dn[nb][c];
-        if (l == 1) {
+      };
+      for (int l = L - 1; l >= 1; l -= 2) {
+        chunk_t t2[NB][CHh];
+        adj(l, d, t2);
+        if (l - 1 >= 1) {
+          adj(l - 1, t2, d);
+        } else {
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int c = 0; c < CHh; ++c) dstash(0)[(nb * CHh + c) * 64 + lane] = d[nb][c];
+            for (int c = 0; c < CHh; ++c) d[nb][c] = t2[nb][c];
         }
+      }
+      if (L > 1) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int c = 0; c < CHh; ++c)
+            T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
       }
     }
   }
@@ -721,7 +827,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp(MlpArgs a) {
   if (MODE == MODE_FUSED) {
     sloss[threadIdx.x] = lossacc;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = WAVES_PER_WG * 32; o > 0; o >>= 1) {
       if (threadIdx.x < o) sloss[threadIdx.x] += sloss[threadIdx.x + o];
       __syncthreads();
     }
@@ -1060,11 +1166,14 @@ hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* 
 template <int PREC, int IN, int H>
 static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st) {
   if (mode == MODE_FWD)
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
+                       st, a);
   else if (mode == MODE_BWD)
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
+                       st, a);
   else
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED>), dim3(grid), dim3(Prec<PREC>::WAVES * 64),
+                       0, st, a);
   return hipGetLastError();
 }
 
@@ -1074,6 +1183,23 @@ hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int g
   if (in == I && h == HH)                                                          \
     return prec == PREC_BF16 ? mlp_impl<PREC_BF16, I, HH>(mode, a, grid, st)       \
                              : mlp_impl<PREC_F32, I, HH>(mode, a, grid, st);
+  DINR_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <int PREC, int IN, int H>
+static hipError_t query_impl(const MlpArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_QUERY>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(int prec, int in, int h, const MlpArgs& a, int grid, hipStream_t st) {
+#define X(I, HH)                                                          \
+  if (in == I && h == HH)                                                 \
+    return prec == PREC_BF16 ? query_impl<PREC_BF16, I, HH>(a, grid, st)  \
+                             : query_impl<PREC_F32, I, HH>(a, grid, st);
   DINR_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;

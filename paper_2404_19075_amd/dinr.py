@@ -48,6 +48,11 @@ class Sampling(C.Structure):
                 ("n_max", C.c_int32), ("h", C.c_double)]
 
 
+class Request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("z_or_theta", C.c_double),
+                ("t", C.c_double), ("samples_per_ray", C.c_int32), ("reserved", C.c_int32)]
+
+
 class Adam(C.Structure):
     _fields_ = [("m_d", C.c_void_p), ("v_d", C.c_void_p), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
@@ -56,7 +61,10 @@ class Adam(C.Structure):
 
 EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
-           "dinr_profile_enable", "dinr_profile_read"]
+           "dinr_profile_enable", "dinr_profile_read", "dinr_server_create", "dinr_server_destroy",
+           "dinr_query", "dinr_poll", "dinr_query_wait", "dinr_query_release",
+           "dinr_server_stats"]
+QUERY_SLICE, QUERY_REPROJECTION = 0, 1
 PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
 
 _lib = None
@@ -92,6 +100,22 @@ def load(path: str = LIB_PATH):
     L.dinr_profile_enable.restype = i32
     L.dinr_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.dinr_profile_read.restype = i32
+    L.dinr_server_create.argtypes = [vp, vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
+    L.dinr_server_create.restype = i32
+    L.dinr_server_destroy.argtypes = [vp]
+    L.dinr_server_destroy.restype = i32
+    L.dinr_query.argtypes = [vp, C.POINTER(Request), vp, C.POINTER(C.c_uint64)]
+    L.dinr_query.restype = i32
+    L.dinr_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.dinr_poll.restype = i32
+    L.dinr_query_wait.argtypes = [vp, C.c_uint64]
+    L.dinr_query_wait.restype = i32
+    L.dinr_query_release.argtypes = [vp, C.c_uint64]
+    L.dinr_query_release.restype = i32
+    L.dinr_server_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_size_t), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]
+    L.dinr_server_stats.restype = i32
     _lib = L
     return L
 
@@ -214,6 +238,57 @@ class Context:
         n = C.c_int64()
         self._check(self._lib.dinr_profile_read(self._h, kind, C.byref(t), C.byref(n)))
         return t.value, n.value
+
+
+class Server:
+    """Continuously batched queries of a trained field (slices, reprojections)."""
+
+    def __init__(self, ctx: "Context", params, mem_budget: int = 1 << 30, max_active: int = 64):
+        self._ctx = ctx
+        self._params = params  # must stay alive and unchanged
+        h = C.c_void_p()
+        ctx._check(ctx._lib.dinr_server_create(ctx._h, _ptr(params), int(mem_budget),
+                                               int(max_active), C.byref(h)))
+        self._h = h
+        self._lib = ctx._lib
+
+    def submit(self, kind: int, n: int, z_or_theta: float, t: float, out,
+               samples_per_ray: int = 0) -> int:
+        r = Request(kind, n, z_or_theta, t, samples_per_ray, 0)
+        tk = C.c_uint64()
+        self._ctx._check(self._lib.dinr_query(self._h, C.byref(r), _ptr(out), C.byref(tk)))
+        return tk.value
+
+    def poll(self, ticket: int):
+        """(done, latency_ms)."""
+        d = C.c_int32()
+        lat = C.c_double()
+        self._ctx._check(self._lib.dinr_poll(self._h, ticket, C.byref(d), C.byref(lat)))
+        return bool(d.value), lat.value
+
+    def wait(self, ticket: int):
+        self._ctx._check(self._lib.dinr_query_wait(self._h, ticket))
+
+    def release(self, ticket: int):
+        self._ctx._check(self._lib.dinr_query_release(self._h, ticket))
+
+    def stats(self):
+        a, b, c, d, e = C.c_int64(), C.c_int64(), C.c_size_t(), C.c_int32(), C.c_int32()
+        self._ctx._check(self._lib.dinr_server_stats(self._h, C.byref(a), C.byref(b), C.byref(c),
+                                                     C.byref(d), C.byref(e)))
+        return dict(launches=a.value, tiles=b.value, bytes_in_use=c.value, queued=d.value,
+                    admitted=e.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dinr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def project_function():

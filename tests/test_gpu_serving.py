@@ -1,0 +1,164 @@
+"""Queries of a trained field through the continuously batched server.
+
+Slices are checked against the oracle's field at the same points, and
+reprojections against the oracle's forward projection of the same rays
+(tolerances as for the step: FP32 1e-4, BF16 2e-2 norm-wise).  A request's
+output must be bitwise identical whether it runs alone or among requests of
+other sizes arriving while it is on the GPU, and admission must respect the
+memory budget.
+"""
+import dataclasses
+import math
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_19075_amd import synth as S
+
+from helpers import log, make_ctx, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = 0, 1
+TOL = {FP32: 1e-4, BF16: 2e-2}
+
+
+def server_for(w, b, prec, budget=1 << 28, max_active=64):
+    from paper_2404_19075_amd import dinr
+    ctx = make_ctx(w, b.B, prec)
+    P = torch.tensor(b.params, device="cuda")
+    srv = dinr.Server(ctx, P, mem_budget=budget, max_active=max_active)
+    return ctx, P, srv
+
+
+def slice_points(g, n, z, t):
+    lo = np.array(g.fov[0::2])
+    hi = np.array(g.fov[1::2])
+    c = (np.arange(n) + 0.5) / n
+    xs = lo[0] + c * (hi[0] - lo[0])
+    ys = lo[1] + c * (hi[1] - lo[1])
+    X, Y = np.meshgrid(xs, ys)  # row i <-> y, column j <-> x
+    return np.column_stack([X.ravel(), Y.ravel(), np.full(n * n, z), np.full(n * n, t)])
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_slice_matches_oracle_field(prec):
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c0", n_rays=8)
+    w = b.workload
+    ctx, P, srv = server_for(w, b, prec)
+    n, z, t = 48, 0.13, 0.37
+    out = torch.empty(n * n, device="cuda")
+    tk = srv.submit(dinr.QUERY_SLICE, n, z, t, out)
+    srv.wait(tk)
+    got = out.cpu().numpy()
+    ref = O.field_points(w.geom, w.mlp, b.B, b.params, slice_points(w.geom, n, z, t))
+    e = rel(got, ref)
+    log(f"  slice prec={prec} rel err {e:.3e}")
+    assert e <= TOL[prec]
+    srv.close()
+    ctx.close()
+
+
+def reprojection_geometry(g, n, theta, t):
+    """The scanner geometry reduced to one view at (theta, t) with an n x n
+    detector of the same extent."""
+    return dataclasses.replace(g, rows=n, cols=n, n_views=1, pitch_u=g.pitch_u * g.cols / n,
+                               pitch_v=g.pitch_v * g.rows / n, theta=np.array([theta]),
+                               time=np.array([t]))
+
+
+@pytest.mark.parametrize("prec,S_", [(FP32, 32), (BF16, 64)])
+def test_reprojection_matches_oracle_projection(prec, S_):
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c0", n_rays=8)
+    w = b.workload
+    ctx, P, srv = server_for(w, b, prec)
+    n, theta, t = 40, 0.7, 0.55
+    out = torch.empty(n * n, device="cuda")
+    tk = srv.submit(dinr.QUERY_REPROJECTION, n, theta, t, out, samples_per_ray=S_)
+    srv.wait(tk)
+    got = out.cpu().numpy()
+    g1 = reprojection_geometry(w.geom, n, theta, t)
+    ref, nref, _, _ = O.forward(g1, w.mlp, S.Sampling(mode=0, n=S_), b.B, b.params,
+                                np.arange(n * n))
+    miss = nref == 0
+    log(f"  reprojection prec={prec} misses {int(miss.sum())} rel err {rel(got, ref):.3e}")
+    assert np.all(got[miss] == 0)
+    assert rel(got, ref) <= TOL[prec]
+    srv.close()
+    ctx.close()
+
+
+def test_alone_equals_mix_bitwise():
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c0", n_rays=8)
+    w = b.workload
+    ctx, P, srv = server_for(w, b, BF16)
+    # the request under test, alone
+    outA = torch.zeros(96 * 96, device="cuda")
+    srv.wait(srv.submit(dinr.QUERY_REPROJECTION, 96, 1.1, 0.2, outA, samples_per_ray=64))
+    alone = outA.cpu().numpy().copy()
+    outS = torch.zeros(64 * 64, device="cuda")
+    srv.wait(srv.submit(dinr.QUERY_SLICE, 64, -0.3, 0.8, outS))
+    alone_s = outS.cpu().numpy().copy()
+    # the same requests among others of different sizes, submitted while the
+    # earlier ones are still running
+    outs = []
+    tickets = []
+    sizes = [(dinr.QUERY_SLICE, 256), (dinr.QUERY_REPROJECTION, 128), (dinr.QUERY_SLICE, 32),
+             (dinr.QUERY_REPROJECTION, 64)]
+    for k, (kind, n) in enumerate(sizes):
+        o = torch.zeros(n * n, device="cuda")
+        outs.append(o)
+        tickets.append(srv.submit(kind, n, 0.1 * k, 0.1 * k, o, samples_per_ray=64))
+        if k == 1:
+            outA.zero_()
+            torch.cuda.synchronize()
+            tA = srv.submit(dinr.QUERY_REPROJECTION, 96, 1.1, 0.2, outA, samples_per_ray=64)
+            outS.zero_()
+            torch.cuda.synchronize()
+            tS = srv.submit(dinr.QUERY_SLICE, 64, -0.3, 0.8, outS)
+    for tk in tickets + [tA, tS]:
+        srv.wait(tk)
+    st = srv.stats()
+    log(f"  server stats {st}")
+    assert np.array_equal(outA.cpu().numpy(), alone)
+    assert np.array_equal(outS.cpu().numpy(), alone_s)
+    srv.close()
+    ctx.close()
+
+
+def test_admission_by_memory_budget():
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c0", n_rays=8)
+    w = b.workload
+    n = 128
+    ctx, P, srv = server_for(w, b, BF16, budget=2 * n * n * 4, max_active=16)
+    big = torch.empty(256 * 256, device="cuda")
+    with pytest.raises(dinr.DinrError) as ei:
+        srv.submit(dinr.QUERY_SLICE, 256, 0.0, 0.5, big)
+    assert ei.value.code == dinr.ENOMEM
+    outs = [torch.zeros(n * n, device="cuda") for _ in range(6)]
+    tks = [srv.submit(dinr.QUERY_REPROJECTION, n, 0.3 * k, 0.1 * k, o, samples_per_ray=64)
+           for k, o in enumerate(outs)]
+    peak_admitted = 0
+    while True:
+        st = srv.stats()
+        peak_admitted = max(peak_admitted, st["admitted"])
+        assert st["bytes_in_use"] <= 2 * n * n * 4
+        if all(srv.poll(t)[0] for t in tks):
+            break
+        time.sleep(0.001)
+    log(f"  peak admitted {peak_admitted}")
+    assert peak_admitted <= 2
+    # results are those of the same requests run alone
+    for k, o in enumerate(outs):
+        ref = torch.zeros(n * n, device="cuda")
+        srv.wait(srv.submit(dinr.QUERY_REPROJECTION, n, 0.3 * k, 0.1 * k, ref, samples_per_ray=64))
+        assert torch.equal(ref, o)
+    srv.close()
+    ctx.close()
