@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workspace-gb", type=float, default=120.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the query-serving run")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (to scale the memory "
+                         "counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU's share of the batch; this build has no multi-GPU "
@@ -198,6 +201,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * (1 << 30)) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {4 * n} bytes")
+        return
     from paper_2404_19075_amd import dinr
     from paper_2404_19075_amd import synth as S
     dinr.load()

@@ -8,7 +8,7 @@
 #include <cstdio>
 #include <vector>
 
-#include "../../include/dinr.h"
+#include "dinr.h"
 #include "kernels.h"
 
 using namespace dinr;
