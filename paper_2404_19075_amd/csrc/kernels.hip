@@ -271,9 +271,14 @@ __device__ inline void sincos_rev(float f, float* s, float* c) {
 // all waves and the other buffer is no longer being read.
 constexpr int PANEL_BYTES = 32768;
 
+// Output blocks per panel: as many as fit, but at most half the layer, so that
+// every layer has an even number of panels and starts in buffer 0.  The buffer
+// a panel lives in is then known at compile time, and the two buffers being
+// distinct LDS objects lets the compiler see that reading one does not have to
+// wait for the DMA into the other.
 template <int KC, int H>
 __host__ __device__ constexpr int panel_obs() {
-  return (PANEL_BYTES / (KC * 1024)) > H / 32 ? H / 32
+  return (PANEL_BYTES / (KC * 1024)) > H / 64 ? H / 64
          : (PANEL_BYTES / (KC * 1024)) < 1     ? 1
                                                 : PANEL_BYTES / (KC * 1024);
 }
@@ -282,18 +287,70 @@ __host__ __device__ constexpr int panel_bytes() { return panel_obs<KC, H>() * KC
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-// bytes: a multiple of 1 KB times the wave count.  Wave w of nw copies the
-// 1 KB blocks w, w+nw, ...; the LDS destination of one instruction is
-// wave-uniform.
+// A per-lane byte offset the optimizer cannot see through: it is recomputed
+// where it is used (one VALU op from the lane id) instead of being hoisted
+// out of the tile loop as one 64-bit address per panel, which would not fit
+// in registers and would come back from scratch memory.
+__device__ inline uint32_t lane_off(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Forces a 16-byte chunk to be computed at this point of the program (an
+// opaque use ordered with the other volatile asm, e.g. the panel barrier).
+template <class C>
+__device__ inline void pin(C& v) {
+  static_assert(sizeof(C) == 16, "16-byte chunk");
+  typedef int i32x4 __attribute__((ext_vector_type(4)));
+  i32x4 t = __builtin_bit_cast(i32x4, v);
+  asm volatile("" : "+v"(t));
+  v = __builtin_bit_cast(C, t);
+}
+
+// bytes: a multiple of 1 KB.  Wave w of nw copies the 1 KB blocks w, w+nw,
+// ...; the LDS destination of one instruction is wave-uniform.
 template <int NW>
 __device__ inline void dma_panel(const char* __restrict__ src, char* dst, int bytes, int w,
                                  int lane) {
-  for (int off = w * 1024; off < bytes; off += NW * 1024)
-    __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 16), (lds_void*)(dst + off),
-                                     16, 0, 0);
+  uint32_t lo = lane_off((uint32_t)(w * 1024 + lane * 16));
+  for (int off = w * 1024; off < bytes; off += NW * 1024, lo += NW * 1024)
+    __builtin_amdgcn_global_load_lds((const void*)(src + lo), (lds_void*)(dst + off), 16, 0, 0);
 }
 
-__device__ inline void wait_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// One layer's H biases (fp32) into LDS with a single wave instruction.
+template <int H>
+__device__ inline void dma_bias(const float* __restrict__ src, float* dst, int lane) {
+  constexpr int SZ = H * 4 / WAVE;  // bytes per lane
+  static_assert(SZ == 4 || SZ == 16, "one DMA instruction per layer's biases");
+  const void* p = (const void*)((const char*)src + lane_off((uint32_t)(lane * SZ)));
+  if constexpr (SZ == 16) __builtin_amdgcn_global_load_lds(p, (lds_void*)dst, 16, 0, 0);
+  else __builtin_amdgcn_global_load_lds(p, (lds_void*)dst, 4, 0, 0);
+}
+
+
+// Workgroup barrier for the panel exchange.  It orders LDS traffic (and the
+// DMA into LDS that each wave has already waited for) but, unlike
+// __syncthreads, whose release fence waits for every outstanding global
+// store, leaves the wave's stash stores in flight.
+__device__ inline void panel_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Wait until at most N vector-memory operations are outstanding.  Vector
+// memory operations complete in issue order, so when exactly N stash stores
+// were issued after a panel's DMA, vmcnt(N) waits for that DMA but not for
+// the stores: they drain while the next panel computes.
+// Issued through the builtin, not inline asm, so that the compiler's own
+// wait insertion knows what has completed (gfx9 encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their maxima).
+template <int N>
+__device__ inline void wait_vm() {
+  static_assert(N >= 0 && N <= 63, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // One fully connected layer for the wave's NB point blocks:
 //   y = act(W x + b)   (EPI_RELU_BIAS; ReLU mask bits go to msk)
@@ -340,6 +397,10 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
       bits |= (neg_u32((uint32_t)r) >> 31) << e;
     }
     msk[mw] |= bits << sh;
+    // fold the bits in now: left to itself the compiler defers this to the
+    // store of the mask words after the layer and keeps every negated
+    // value of the layer alive until then
+    asm volatile("" : "+v"(msk[mw]));
   } else {
     const uint32_t bits = msk[mw] >> sh;
 #pragma unroll
@@ -356,17 +417,20 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
 //   y = (W x) . mask   (EPI_MASK; mask bits come from msk)
 // W: the layer's packed fragments in global memory, streamed through LDS.
 // Wnext/next_bytes: first panel of whatever follows in the sequence (or null).
+// sbias: this layer's biases in LDS (EPI_RELU_BIAS).  gbias_next (nullable):
+// biases of the next forward layer, copied into sbias_next with the last panel.
 // stash (nullable): where to store x for the weight gradient.
 // Instruction stream per K-step: 2 MFMAs (one per point block), one LDS read
 // of the fragment D steps ahead, and a slice of the previous output block's
 // epilogue, so VALU work and LDS latency overlap the matrix cores.
-template <int PREC, int KC, int H, int EPI>
+template <int PREC, int KC, int H, int EPI, int VM_ENTRY>
 __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>::NB][KC],
                              typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
                              const char* __restrict__ W, const char* __restrict__ Wnext,
-                             int next_bytes, const float* __restrict__ bias,
+                             int next_bytes, const float* sbias,
+                             const float* __restrict__ gbias_next, float* sbias_next,
                              uint32_t (&msk)[mask_words<PREC, H>()],
-                             typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW, int& buf,
+                             typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW0, char* sW1,
                              int lane, int w, int z) {
   using T = Prec<PREC>;
   using chunk_t = typename T::chunk_t;
@@ -378,7 +442,11 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
   constexpr int PB = panel_bytes<KC, H>();
   constexpr int D = 3;  // LDS prefetch distance (K-steps)
   constexpr int MFMA_PER_STEP = (PREC == PREC_BF16 ? 1 : 4) * NB;
+  constexpr int NP = OB / OBP;          // panels in this layer
+  constexpr int SPP = KC / NP;          // stash chunks per point block stored per panel
   static_assert(OB % OBP == 0, "panels must tile the output blocks");
+  static_assert(KC % NP == 0, "stash stores must spread evenly over the panels");
+  static_assert(NP % 2 == 0, "each layer starts and ends in buffer 0");
   const int hf = lane >> 5;
   if (EPI == EPI_RELU_BIAS)
 #pragma unroll
@@ -387,27 +455,42 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 #pragma unroll
   for (int ob = 0; ob < OB; ++ob) {
     if (ob % OBP == 0) {
-      wait_dma();
-      __syncthreads();
-      char* nxt = sW + (buf ^ 1) * PANEL_BYTES;
+      const int pi = ob / OBP;
+      // the panel DMA'd last is complete; stores issued after it may still drain
+      // (every layer of a call stashes or none does, so a null stash here
+      // means the previous layer issued no stores either)
+      if (stash) {
+        if (pi == 0) wait_vm<VM_ENTRY>();
+        else wait_vm<NB * SPP>();
+      } else {
+        wait_vm<0>();
+      }
+      panel_barrier();
+      char* nxt = (pi & 1) ? sW0 : sW1;
+      // the next layer's biases: the previous reader of their buffer (two
+      // layers back) finished before this layer's first barrier
+      if (pi == 0 && gbias_next && w == 0) dma_bias<H>(gbias_next, sbias_next, lane);
       if (ob + OBP < OB) dma_panel<T::WAVES>(W + (ob / OBP + 1) * PB, nxt, PB, w, lane);
       else if (Wnext) dma_panel<T::WAVES>(Wnext, nxt, next_bytes, w, lane);
-      if (ob == 0 && stash) {
+      asm volatile("" ::: "memory");  // the stores below stay after the DMA
+      if (stash) {
+        // this panel's share of the layer input for the weight gradient
+        char* sp = (char*)stash + lane_off((uint32_t)(lane * sizeof(chunk_t)));
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int c = 0; c < KC; ++c)
-            T::store_nt(&stash[(nb * KC + c) * 64 + lane], x[nb][c]);
+          for (int c = pi * SPP; c < (pi + 1) * SPP; ++c)
+            T::store_nt((chunk_t*)(sp + (nb * KC + c) * 64 * sizeof(chunk_t)), x[nb][c]);
       }
     }
     const chunk_t* __restrict__ Wp =
-        (const chunk_t*)(sW + buf * PANEL_BYTES) + (ob % OBP) * KC * 64;
+        (const chunk_t*)(((ob / OBP) & 1) ? sW1 : sW0) + (ob % OBP) * KC * 64;
     f32x16 acc[NB];
     if (EPI == EPI_RELU_BIAS) {
       float bq[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float4 b4 = *(const float4*)(bias + z + 32 * ob + 8 * q + 4 * hf);
+        const float4 b4 = *(const float4*)(sbias + z + 32 * ob + 8 * q + 4 * hf);
         bq[4 * q + 0] = b4.x; bq[4 * q + 1] = b4.y; bq[4 * q + 2] = b4.z; bq[4 * q + 3] = b4.w;
       }
 #pragma unroll
@@ -423,7 +506,9 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     chunk_t a[D + 1];
 #pragma unroll
     for (int c = 0; c < D && c < KC; ++c) a[c] = Wp[c * 64 + lane];
-    __builtin_amdgcn_sched_group_barrier(0x100, D < KC ? D : KC, 0);
+    // the bias reads (EPI_RELU_BIAS) and the first D fragment reads lead the block
+    __builtin_amdgcn_sched_group_barrier(0x100, (D < KC ? D : KC) + (EPI == EPI_RELU_BIAS ? 4 : 0),
+                                         0);
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
       if (c + D < KC) a[(c + D) % (D + 1)] = Wp[(c + D) * 64 + lane];
@@ -440,7 +525,6 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) accp[nb] = acc[nb];
-    if ((ob + 1) % OBP == 0) buf ^= 1;
   }
 #pragma unroll
   for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk);
@@ -458,9 +542,14 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
   constexpr int MSK_LAYERS = (MODE != MODE_FWD) ? MAX_LAYERS - 1 : 1;
   constexpr int PB_IN = panel_bytes<CI, H>(), PB_H = panel_bytes<CHh, H>();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, hf = lane >> 5, pl = lane & 31;
+  // the wave index in a scalar register: every address derived from it
+  // (stash blocks, LDS slices, DMA destinations) is then wave-uniform too
+  const int lane = threadIdx.x & 63, hf = lane >> 5, pl = lane & 31;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  __shared__ __align__(16) char sW[2 * PANEL_BYTES];
+  // weight panels: two separate arrays (see panel_obs)
+  __shared__ __align__(16) char sW0[PANEL_BYTES];
+  __shared__ __align__(16) char sW1[PANEL_BYTES];
   __shared__ float4 sB[C];
   __shared__ float sval[TILE];
   __shared__ int32_t srid[TILE];
@@ -468,6 +557,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   __shared__ float swgt[TILE];  // query mode: weight mu0 l / n of each point's ray
   __shared__ double sloss[WAVES_PER_WG * 64];
   __shared__ float sdwo[WAVES_PER_WG][H + 1];
+  // biases: layer 0 (loaded once), odd and even hidden layers (each copied in
+  // during the layer before); w_o in register-slot order.  Separate arrays,
+  // selected at compile time, so reads never wait for an unrelated DMA.
+  __shared__ __align__(16) float sBias0[H];
+  __shared__ __align__(16) float sBiasOdd[H];
+  __shared__ __align__(16) float sBiasEven[H];
+  __shared__ __align__(16) float sWo[H];
   // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
 
@@ -486,10 +582,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   auto Wl = [&](int l) { return Wpk + a.wpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
   auto WTl = [&](int l) { return WTpk + a.wtpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
 
-  int buf = 0;
   const int64_t t0 = (QUERY ? 0 : a.tile_begin) + blockIdx.x;
-  if (t0 < t_end) dma_panel<WAVES_PER_WG>(Wl(0), sW, PB_IN, w, lane);
+  if (t0 < t_end) dma_panel<WAVES_PER_WG>(Wl(0), sW0, PB_IN, w, lane);
   for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
+  for (int k = threadIdx.x; k < H; k += blockDim.x) {
+    sBias0[k] = a.bias[k];
+    sWo[k] = a.wo_perm[k];
+  }
   if (MODE != MODE_FWD)
     for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
   __syncthreads();
@@ -580,6 +679,11 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         }
         x0[nb][c] = T::from_f32(cv);
         x0[nb][c + CI / 2] = T::from_f32(sv);
+        // materialise the encoded chunk here: otherwise the arithmetic sinks
+        // past the first panel barrier to its use, and the B rows of every
+        // chunk stay live across it
+        pin(x0[nb][c]);
+        pin(x0[nb][c + CI / 2]);
       }
     }
     const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
@@ -589,6 +693,10 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
     };
     // what follows the last forward layer in the panel sequence
     const char* after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : nullptr);
+    // biases of layer l+1 (none after the last layer: layer 0's stay resident)
+    auto bias_next = [&](int l) -> const float* {
+      return l + 1 < L ? a.bias + (l + 1) * H : nullptr;
+    };
     const int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
     // ---- hidden layers (Appendix B item 3)
     chunk_t y[NB][CHh];
@@ -596,29 +704,38 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       uint32_t mk[MSK_PER_LAYER];
       const char* nx = L > 1 ? Wl(1) : after_fwd;
       const int nxb = L > 1 ? PB_H : after_fwd_bytes;
-      layer<PREC, CI, H, EPI_RELU_BIAS>(x0, y, Wl(0), nx, nxb, a.bias, mk, hstash(0, CI), sW, buf,
-                                        lane, w, z);
+      layer<PREC, CI, H, EPI_RELU_BIAS, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
+                                           mk, hstash(0, CI), sW0, sW1, lane, w, z);
       if (BWD_PART && L > 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
     // hidden layers 2..L, two per iteration with the roles of y and z swapped
     // so that no activation array is copied between layers
-    auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
+    // sb: this layer's biases, sbn: where the next layer's go
+    auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh],
+                      const float* sb, float* sbn) {
       uint32_t mk[MSK_PER_LAYER];
       const char* nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
       const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
-      layer<PREC, CHh, H, EPI_RELU_BIAS>(in, out, Wl(l), nx, nxb, a.bias + l * H, mk,
-                                         hstash(l, CHh), sW, buf, lane, w, z);
+      // stores the previous layer issued after its last DMA: its last panel's share
+      constexpr int VM_1 = BWD_PART ? NB * (CI / (H / 32 / panel_obs<CI, H>())) : 0;
+      constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
+      if (VM_1 != VM_H && l == 1)
+        layer<PREC, CHh, H, EPI_RELU_BIAS, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                 hstash(l, CHh), sW0, sW1, lane, w, z);
+      else
+        layer<PREC, CHh, H, EPI_RELU_BIAS, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                 hstash(l, CHh), sW0, sW1, lane, w, z);
       if (BWD_PART && l < L - 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     };
     for (int l = 1; l < L; l += 2) {
       chunk_t t2[NB][CHh];
-      hidden(l, y, t2);
+      hidden(l, y, t2, sBiasOdd, sBiasEven);
       if (l + 1 < L) {
-        hidden(l + 1, t2, y);
+        hidden(l + 1, t2, y, sBiasEven, sBiasOdd);
       } else {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
@@ -630,7 +747,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
     float zo[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
-    const float* wop = a.wo_perm + z + hf * (H / 2);
+    const float* wop = sWo + z + hf * (H / 2);
 #pragma unroll
     for (int c = 0; c < CHh; ++c) {
 #pragma unroll
@@ -791,8 +908,10 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
         const char* nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : nullptr);
         const int nxb = l > 1 ? PB_H : PB_IN;
-        layer<PREC, CHh, H, EPI_MASK>(in, out, WTl(l), nx, nxb, nullptr, mk, dstash(l), sW, buf,
-                                      lane, w, z);
+        // entering from the forward's last layer or from the previous adjoint
+        // layer: both stored their last panel's share of a width-H input
+        layer<PREC, CHh, H, EPI_MASK, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
+            in, out, WTl(l), nx, nxb, nullptr, nullptr, nullptr, mk, dstash(l), sW0, sW1, lane, w, z);
       };
       for (int l = L - 1; l >= 1; l -= 2) {
         chunk_t t2[NB][CHh];
@@ -815,7 +934,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       }
     }
   }
-  wait_dma();
+  wait_vm<0>();
   if (BWD_PART) {
     __syncthreads();
     for (int f = threadIdx.x; f <= H; f += blockDim.x) {
