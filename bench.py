@@ -166,6 +166,29 @@ def serving(batch, params_np, duration_s=4.0, rates=(0.25, 0.5, 0.9), seed=7):
     return out
 
 
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
+    when the summary does not cover this build of the kernel."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "hbm_traffic_c2_bf16.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and not line.startswith("#"):
+            vals[parts[0]] = parts[1]
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_19075_amd",
+                       "csrc", "kernels.hip")
+    import hashlib
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    key = f"{kernel}_bytes_per_launch"
+    if vals.get("kernels_hip_sha256_16") != digest or key not in vals:
+        return None
+    return float(vals[key])
+
+
 def cpu_baseline(batch, n_rays=192):
     """The FP64 oracle as it stands, on a bounded ray subset of the same batch."""
     from oracle import oracle as O
@@ -257,6 +280,13 @@ def main():
                                  alg_tflops=alg[k] / (kern[k]["ms_per_step"] * 1e-3) / 1e12)
                          for k in kern},
                 step_frac=(f_all * P_pts / (ms_bf16 * 1e-3)) / PEAK["bf16"])
+    # sustained matrix-core rate of this device: operands in registers, and
+    # with the A operand streamed from LDS as in the MLP layers
+    probe = dict(mfma_registers=dinr.probe_mfma(0, 20000), mfma_lds_operand=dinr.probe_mfma(1, 20000))
+    log(f"measured BF16 MFMA rate (TFLOP/s): {probe}")
+    roof["measured_peak_tflops"] = probe
+    roof["frac_of_measured_peak"] = roof["achieved"] / probe["mfma_registers"]
+    roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
     cpu = None if args.no_cpu else cpu_baseline(batch)
     out = {

@@ -253,6 +253,18 @@ enum {
 int dinr_profile_enable(dinr_ctx* ctx, int enable);
 int dinr_profile_read(dinr_ctx* ctx, int kind, double* total_ms, int64_t* launches);
 
+/* Sustained BF16 matrix-core rate of the current device (a measurement aid
+ * for rooflines, not part of the method).  One workgroup of 8 waves per
+ * compute unit; every wave issues `iters` blocks of 16 dependent
+ * 32x32x16 BF16 MFMAs.  kind 0: both operands in registers (the matrix
+ * pipe's ceiling).  kind 1: the A operand of each MFMA read from LDS, 16
+ * bytes per lane, three steps ahead (the operand flow of the MLP layers).
+ * Enqueued on `stream` (a hipStream_t, may be null) and waited for; the rate
+ * in TFLOP/s goes to *tflops.  Allocates and frees a 4-byte device buffer.
+ * Returns DINR_EINVAL for an unknown kind or iters <= 0, DINR_EHIP on a
+ * runtime failure. */
+int dinr_probe_mfma(int kind, int64_t iters, void* stream, double* tflops);
+
 #ifdef __cplusplus
 }
 #endif

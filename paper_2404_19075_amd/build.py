@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["dinr_api.hip", "kernels.hip", "server.hip"]
+SOURCES = ["dinr_api.hip", "kernels.hip", "server.hip", "probe.hip"]
 LIB = os.path.join(HERE, "libdinr.so")
 
 FLAGS = [

@@ -151,6 +151,8 @@ static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
     a.wpk_off[l] = p.pk.pk_off[l];
     a.wtpk_off[l] = p.pk.pkT_off[l];
   }
+  a.wpk_bytes = p.pk.n_w * (int64_t)esize(c->prec);
+  a.wtpk_bytes = p.pk.n_wt * (int64_t)esize(c->prec);
   a.L = c->L;
   a.out_act = c->mlp.out_act;
   a.tile_begin = 0;

@@ -70,6 +70,7 @@ struct MlpArgs {
   const float* wo_perm;      // [2][H/2] w_o in register-slot order
   int64_t wpk_off[MAX_LAYERS];
   int64_t wtpk_off[MAX_LAYERS];
+  int64_t wpk_bytes, wtpk_bytes;  // sizes of the packed weight arrays
   int L, out_act;
   int64_t tile_begin, tile_end;
   // forward outputs

@@ -307,24 +307,43 @@ __device__ inline void pin(C& v) {
   v = __builtin_bit_cast(C, t);
 }
 
+// A position in a DMA source: a buffer resource over one device array and a
+// byte offset into it (off < 0: nothing).  The copies into LDS are MUBUF
+// loads with the LDS bit: they count only on vmcnt, so the compiler keeps
+// counted waits on LDS reads while they are in flight (a FLAT-encoded copy
+// would make it drain the LDS queue at every read), and the hardware range
+// check turns a read past the array into zeros instead of a fault.
+struct WSrc {
+  __amdgpu_buffer_rsrc_t r;
+  int off;
+  __device__ WSrc at(int delta) const { return WSrc{r, off + delta}; }
+};
+
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int64_t bytes) {
+  // raw (stride 0) buffer; word 3 selects 32-bit data for untyped loads
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
 // bytes: a multiple of 1 KB.  Wave w of nw copies the 1 KB blocks w, w+nw,
 // ...; the LDS destination of one instruction is wave-uniform.
 template <int NW>
-__device__ inline void dma_panel(const char* __restrict__ src, char* dst, int bytes, int w,
-                                 int lane) {
+__device__ inline void dma_panel(WSrc src, char* dst, int bytes, int w, int lane) {
   uint32_t lo = lane_off((uint32_t)(w * 1024 + lane * 16));
   for (int off = w * 1024; off < bytes; off += NW * 1024, lo += NW * 1024)
-    __builtin_amdgcn_global_load_lds((const void*)(src + lo), (lds_void*)(dst + off), 16, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(src.r, (lds_void*)(dst + off), 16, (int)lo, src.off,
+                                             0, 0);
 }
 
 // One layer's H biases (fp32) into LDS with a single wave instruction.
 template <int H>
-__device__ inline void dma_bias(const float* __restrict__ src, float* dst, int lane) {
+__device__ inline void dma_bias(WSrc src, float* dst, int lane) {
   constexpr int SZ = H * 4 / WAVE;  // bytes per lane
   static_assert(SZ == 4 || SZ == 16, "one DMA instruction per layer's biases");
-  const void* p = (const void*)((const char*)src + lane_off((uint32_t)(lane * SZ)));
-  if constexpr (SZ == 16) __builtin_amdgcn_global_load_lds(p, (lds_void*)dst, 16, 0, 0);
-  else __builtin_amdgcn_global_load_lds(p, (lds_void*)dst, 4, 0, 0);
+  const int lo = (int)lane_off((uint32_t)(lane * SZ));
+  if constexpr (SZ == 16)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(src.r, (lds_void*)dst, 16, lo, src.off, 0, 0);
+  else
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(src.r, (lds_void*)dst, 4, lo, src.off, 0, 0);
 }
 
 
@@ -352,13 +371,32 @@ __device__ inline void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// One fully connected layer for the wave's NB point blocks:
-//   y = act(W x + b)   (EPI_RELU_BIAS; ReLU mask bits go to msk)
-//   y = (W x) . mask   (EPI_MASK; mask bits come from msk)
-// W: the layer's packed fragments in global memory, streamed through LDS.
-// Wnext/next_bytes: first panel of whatever follows in the sequence (or null).
-// stash (nullable): where to store x for the weight gradient.
-enum { EPI_RELU_BIAS = 0, EPI_MASK = 1 };
+// Layer epilogues:
+//   EPI_RELU:      y = relu(W x + b)
+//   EPI_RELU_MASK: the same, and the ReLU mask bits go to msk
+//   EPI_MASK:      y = (W x) . mask, the mask bits coming from msk
+enum { EPI_RELU = 0, EPI_RELU_MASK = 1, EPI_MASK = 2 };
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Packed 16-bit integer max/min/multiply as single instructions (written out:
+// the compiler otherwise turns min(max(h, 0), 1) into per-half compares and
+// selects through lane masks, and splits the bf16 conversions feeding a
+// 16-bit multiply into one conversion per value).
+__device__ inline uint32_t pk_max0_i16(uint32_t x) {
+  uint32_t r;
+  asm("v_pk_max_i16 %0, %1, 0" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ inline uint32_t pk_mul_u16(uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
+__device__ inline uint32_t pk_min1_u16(uint32_t x) {
+  uint32_t r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(r) : "v"(x), "v"(0x00010001u));
+  return r;
+}
 
 template <int PREC, int H>
 __host__ __device__ constexpr int mask_words() { return Prec<PREC>::NB * (H / 32) / 2; }
@@ -377,48 +415,83 @@ template <int PREC, int H, int EPI>
 __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, int k,
                                  typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
                                  uint32_t (&msk)[mask_words<PREC, H>()]) {
-  // Pure integer VALU on the bit patterns (no compares into lane masks):
-  // ReLU is max_i32(bits, 0) (negative floats are negative integers); its
-  // mask bit is the sign of -relu (1 iff z > 0); masking ANDs the value with
-  // the sign-extended bit.
   using T = Prec<PREC>;
   constexpr int VPC = T::VPC, CPO = 16 / VPC, OB = H / 32;
   const int nb = k / CPO, kk = k % CPO;
   const int g = nb * OB + ob;
-  const int mw = g >> 1, sh = 16 * (g & 1) + kk * VPC;
-  float v[VPC];
-  if (EPI == EPI_RELU_BIAS) {
-    uint32_t bits = 0;
+  const int mw = g >> 1;
+  if constexpr (PREC == PREC_BF16) {
+    // Round first, then work on the bf16 pairs, two values per register:
+    // ReLU is max_i16 of the bit patterns (negative values are negative
+    // integers), a unit's mask bit is min_u16(h, 1), and masking multiplies
+    // each half by its 0/1 bit.  Chunk j = 2 (g & 1) + kk of a mask word keeps
+    // the bits of its 4 low halves at 4j..4j+3 and of its high halves at
+    // 16+4j..16+4j+3.
+    float v[8];
 #pragma unroll
-    for (int e = 0; e < VPC; ++e) {
-      const int zi = __float_as_int(acc[nb][kk * VPC + e]);
-      const int r = zi > 0 ? zi : 0;  // v_max_i32
-      v[e] = __int_as_float(r);
-      bits |= (neg_u32((uint32_t)r) >> 31) << e;
+    for (int e = 0; e < 8; ++e) v[e] = acc[nb][kk * 8 + e];
+    u32x4 q = __builtin_bit_cast(u32x4, T::from_f32(v));
+    const int j = 2 * (g & 1) + kk;
+    if (EPI != EPI_MASK) {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        q[d] = pk_max0_i16(q[d]);
+        if (EPI == EPI_RELU_MASK) bits |= pk_min1_u16(q[d]) << d;
+      }
+      if (EPI == EPI_RELU_MASK) {
+        msk[mw] |= bits << (4 * j);
+        // fold the bits in now: left to itself the compiler defers this to
+        // the store of the mask words after the layer and keeps every
+        // intermediate of the layer alive until then
+        asm volatile("" : "+v"(msk[mw]));
+      }
+    } else {
+      const uint32_t bits = msk[mw] >> (4 * j);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        q[d] = pk_mul_u16(q[d], (bits >> d) & 0x00010001u);
+      }
     }
-    msk[mw] |= bits << sh;
-    // fold the bits in now: left to itself the compiler defers this to the
-    // store of the mask words after the layer and keeps every negated
-    // value of the layer alive until then
-    asm volatile("" : "+v"(msk[mw]));
+    y[nb][ob * CPO + kk] = __builtin_bit_cast(typename T::chunk_t, q);
   } else {
-    const uint32_t bits = msk[mw] >> sh;
+    // FP32: integer VALU on the bit patterns (no compares into lane masks).
+    // ReLU is max_i32(bits, 0); its mask bit (bit kk*4+e of the ob's 16) is
+    // the sign of -relu (1 iff z > 0); masking ANDs the value with the
+    // sign-extended bit.
+    const int sh = 16 * (g & 1) + kk * VPC;
+    float v[VPC];
+    if (EPI != EPI_MASK) {
+      uint32_t bits = 0;
 #pragma unroll
-    for (int e = 0; e < VPC; ++e) {
-      const int keep = -(int)((bits >> e) & 1u);  // 0 or all ones
-      v[e] = __int_as_float(__float_as_int(acc[nb][kk * VPC + e]) & keep);
+      for (int e = 0; e < VPC; ++e) {
+        const int zi = __float_as_int(acc[nb][kk * VPC + e]);
+        const int r = zi > 0 ? zi : 0;  // v_max_i32
+        v[e] = __int_as_float(r);
+        if (EPI == EPI_RELU_MASK) bits |= (neg_u32((uint32_t)r) >> 31) << e;
+      }
+      if (EPI == EPI_RELU_MASK) {
+        msk[mw] |= bits << sh;
+        asm volatile("" : "+v"(msk[mw]));
+      }
+    } else {
+      const uint32_t bits = msk[mw] >> sh;
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) {
+        const int keep = -(int)((bits >> e) & 1u);  // 0 or all ones
+        v[e] = __int_as_float(__float_as_int(acc[nb][kk * VPC + e]) & keep);
+      }
     }
+    y[nb][ob * CPO + kk] = T::from_f32(v);
   }
-  y[nb][ob * CPO + kk] = T::from_f32(v);
 }
 
-// One fully connected layer for the wave's NB point blocks:
-//   y = act(W x + b)   (EPI_RELU_BIAS; ReLU mask bits go to msk)
-//   y = (W x) . mask   (EPI_MASK; mask bits come from msk)
+// One fully connected layer for the wave's NB point blocks, with one of the
+// epilogues above.
 // W: the layer's packed fragments in global memory, streamed through LDS.
-// Wnext/next_bytes: first panel of whatever follows in the sequence (or null).
-// sbias: this layer's biases in LDS (EPI_RELU_BIAS).  gbias_next (nullable):
-// biases of the next forward layer, copied into sbias_next with the last panel.
+// Wnext/next_bytes: first panel of whatever follows in the sequence (or none).
+// sbias: this layer's biases in LDS (EPI_RELU, EPI_RELU_MASK).  gbias_next (or
+// none): biases of the next forward layer, copied into sbias_next.
 // stash (nullable): where to store x for the weight gradient.
 // Instruction stream per K-step: 2 MFMAs (one per point block), one LDS read
 // of the fragment D steps ahead, and a slice of the previous output block's
@@ -426,9 +499,8 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
 template <int PREC, int KC, int H, int EPI, int VM_ENTRY>
 __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>::NB][KC],
                              typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
-                             const char* __restrict__ W, const char* __restrict__ Wnext,
-                             int next_bytes, const float* sbias,
-                             const float* __restrict__ gbias_next, float* sbias_next,
+                             WSrc W, WSrc Wnext, int next_bytes, const float* sbias,
+                             WSrc gbias_next, float* sbias_next,
                              uint32_t (&msk)[mask_words<PREC, H>()],
                              typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW0, char* sW1,
                              int lane, int w, int z) {
@@ -448,7 +520,7 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
   static_assert(KC % NP == 0, "stash stores must spread evenly over the panels");
   static_assert(NP % 2 == 0, "each layer starts and ends in buffer 0");
   const int hf = lane >> 5;
-  if (EPI == EPI_RELU_BIAS)
+  if (EPI == EPI_RELU_MASK)
 #pragma unroll
     for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
   f32x16 accp[NB];
@@ -469,9 +541,9 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
       char* nxt = (pi & 1) ? sW0 : sW1;
       // the next layer's biases: the previous reader of their buffer (two
       // layers back) finished before this layer's first barrier
-      if (pi == 0 && gbias_next && w == 0) dma_bias<H>(gbias_next, sbias_next, lane);
-      if (ob + OBP < OB) dma_panel<T::WAVES>(W + (ob / OBP + 1) * PB, nxt, PB, w, lane);
-      else if (Wnext) dma_panel<T::WAVES>(Wnext, nxt, next_bytes, w, lane);
+      if (pi == 0 && gbias_next.off >= 0 && w == 0) dma_bias<H>(gbias_next, sbias_next, lane);
+      if (ob + OBP < OB) dma_panel<T::WAVES>(W.at((pi + 1) * PB), nxt, PB, w, lane);
+      else if (Wnext.off >= 0) dma_panel<T::WAVES>(Wnext, nxt, next_bytes, w, lane);
       asm volatile("" ::: "memory");  // the stores below stay after the DMA
       if (stash) {
         // this panel's share of the layer input for the weight gradient
@@ -486,7 +558,7 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     const chunk_t* __restrict__ Wp =
         (const chunk_t*)(((ob / OBP) & 1) ? sW1 : sW0) + (ob % OBP) * KC * 64;
     f32x16 acc[NB];
-    if (EPI == EPI_RELU_BIAS) {
+    if (EPI != EPI_MASK) {
       float bq[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -506,8 +578,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     chunk_t a[D + 1];
 #pragma unroll
     for (int c = 0; c < D && c < KC; ++c) a[c] = Wp[c * 64 + lane];
-    // the bias reads (EPI_RELU_BIAS) and the first D fragment reads lead the block
-    __builtin_amdgcn_sched_group_barrier(0x100, (D < KC ? D : KC) + (EPI == EPI_RELU_BIAS ? 4 : 0),
+    // the bias reads (not EPI_MASK) and the first D fragment reads lead the block
+    __builtin_amdgcn_sched_group_barrier(0x100, (D < KC ? D : KC) + (EPI != EPI_MASK ? 4 : 0),
                                          0);
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
@@ -567,8 +639,6 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   // ReLU masks of h_1 .. h_{L-1} for the adjoint chain
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
 
-  const char* __restrict__ Wpk = (const char*)a.Wpk;
-  const char* __restrict__ WTpk = (const char*)a.WTpk;
   constexpr bool QUERY = MODE == MODE_QUERY;
   const int64_t P = QUERY ? 0 : a.off[a.R];
   const int64_t n_tiles = QUERY ? a.n_qtiles : (P + TILE - 1) / TILE;
@@ -577,10 +647,17 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   const int L = a.L;
   constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED || MODE == MODE_QUERY;
   constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
+  // the adjoint needs the ReLU masks of the forward layers
+  constexpr int FWD_EPI = BWD_PART ? EPI_RELU_MASK : EPI_RELU;
   double lossacc = 0.0;
   const float g_scale = 2.0f / (float)a.R;
-  auto Wl = [&](int l) { return Wpk + a.wpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
-  auto WTl = [&](int l) { return WTpk + a.wtpk_off[l] * (int64_t)sizeof(typename T::elem_t); };
+  const __amdgpu_buffer_rsrc_t rW = buffer_rsrc(a.Wpk, a.wpk_bytes);
+  const __amdgpu_buffer_rsrc_t rWT = buffer_rsrc(a.WTpk, a.wtpk_bytes);
+  const __amdgpu_buffer_rsrc_t rB = buffer_rsrc(a.bias, (int64_t)L * H * sizeof(float));
+  constexpr int ES = sizeof(typename T::elem_t);
+  auto Wl = [&](int l) { return WSrc{rW, (int)(a.wpk_off[l] * ES)}; };
+  auto WTl = [&](int l) { return WSrc{rWT, (int)(a.wtpk_off[l] * ES)}; };
+  const WSrc none{rW, -1};
 
   const int64_t t0 = (QUERY ? 0 : a.tile_begin) + blockIdx.x;
   if (t0 < t_end) dma_panel<WAVES_PER_WG>(Wl(0), sW0, PB_IN, w, lane);
@@ -692,19 +769,19 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
     };
     // what follows the last forward layer in the panel sequence
-    const char* after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : nullptr);
+    const WSrc after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : none);
     // biases of layer l+1 (none after the last layer: layer 0's stay resident)
-    auto bias_next = [&](int l) -> const float* {
-      return l + 1 < L ? a.bias + (l + 1) * H : nullptr;
+    auto bias_next = [&](int l) -> WSrc {
+      return l + 1 < L ? WSrc{rB, (l + 1) * H * (int)sizeof(float)} : none;
     };
     const int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
     // ---- hidden layers (Appendix B item 3)
     chunk_t y[NB][CHh];
     {
       uint32_t mk[MSK_PER_LAYER];
-      const char* nx = L > 1 ? Wl(1) : after_fwd;
+      const WSrc nx = L > 1 ? Wl(1) : after_fwd;
       const int nxb = L > 1 ? PB_H : after_fwd_bytes;
-      layer<PREC, CI, H, EPI_RELU_BIAS, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
+      layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
                                            mk, hstash(0, CI), sW0, sW1, lane, w, z);
       if (BWD_PART && L > 1)
 #pragma unroll
@@ -716,16 +793,16 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
     auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh],
                       const float* sb, float* sbn) {
       uint32_t mk[MSK_PER_LAYER];
-      const char* nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
+      const WSrc nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
       const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
       // stores the previous layer issued after its last DMA: its last panel's share
       constexpr int VM_1 = BWD_PART ? NB * (CI / (H / 32 / panel_obs<CI, H>())) : 0;
       constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
       if (VM_1 != VM_H && l == 1)
-        layer<PREC, CHh, H, EPI_RELU_BIAS, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+        layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
                                                  hstash(l, CHh), sW0, sW1, lane, w, z);
       else
-        layer<PREC, CHh, H, EPI_RELU_BIAS, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+        layer<PREC, CHh, H, FWD_EPI, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
                                                  hstash(l, CHh), sW0, sW1, lane, w, z);
       if (BWD_PART && l < L - 1)
 #pragma unroll
@@ -906,12 +983,12 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         uint32_t mk[MSK_PER_LAYER];
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
-        const char* nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : nullptr);
+        const WSrc nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : none);
         const int nxb = l > 1 ? PB_H : PB_IN;
         // entering from the forward's last layer or from the previous adjoint
         // layer: both stored their last panel's share of a width-H input
         layer<PREC, CHh, H, EPI_MASK, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
-            in, out, WTl(l), nx, nxb, nullptr, nullptr, nullptr, mk, dstash(l), sW0, sW1, lane, w, z);
+            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z);
       };
       for (int l = L - 1; l >= 1; l -= 2) {
         chunk_t t2[NB][CHh];

@@ -222,6 +222,8 @@ static void scheduler(dinr_server* s) {
       a.wpk_off[l] = s->pk.pk_off[l];
       a.wtpk_off[l] = s->pk.pkT_off[l];
     }
+    a.wpk_bytes = s->pk.n_w * (int64_t)esize(c->prec);
+    a.wtpk_bytes = s->pk.n_wt * (int64_t)esize(c->prec);
     a.L = c->L;
     a.out_act = c->mlp.out_act;
     a.qdesc = s->d_desc;

@@ -63,7 +63,7 @@ EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
            "dinr_profile_enable", "dinr_profile_read", "dinr_server_create", "dinr_server_destroy",
            "dinr_query", "dinr_poll", "dinr_query_wait", "dinr_query_release",
-           "dinr_server_stats"]
+           "dinr_server_stats", "dinr_probe_mfma"]
 QUERY_SLICE, QUERY_REPROJECTION = 0, 1
 PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
 
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH):
     L.dinr_profile_enable.restype = i32
     L.dinr_profile_read.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.dinr_profile_read.restype = i32
+    L.dinr_probe_mfma.argtypes = [i32, i64, vp, C.POINTER(C.c_double)]
+    L.dinr_probe_mfma.restype = i32
     L.dinr_server_create.argtypes = [vp, vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
     L.dinr_server_create.restype = i32
     L.dinr_server_destroy.argtypes = [vp]
@@ -289,6 +291,17 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def probe_mfma(kind: int, iters: int) -> float:
+    """Sustained BF16 matrix-core rate in TFLOP/s on the current device:
+    kind 0 register operands, kind 1 A operand from LDS (dinr_probe_mfma)."""
+    lib = load()
+    t = C.c_double(0.0)
+    rc = lib.dinr_probe_mfma(int(kind), int(iters), _stream(), C.byref(t))
+    if rc != 0:
+        raise DinrError(rc, "dinr_probe_mfma failed")
+    return t.value
 
 
 def project_function():
