@@ -93,7 +93,8 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
   const int64_t k_split = 16384;  // points summed by one weight-gradient workgroup
   p->kb = k_split / 32;
   int64_t per_point = 0;  // stash elements per point
-  for (int l = 0; l < c->L; ++l) per_point += (l == 0 ? c->IN : c->H) + c->H;
+  // layer 1's input is stashed as the point's 4 coordinates (16 bytes)
+  for (int l = 0; l < c->L; ++l) per_point += (l == 0 ? 16 / (int)esize(c->prec) : c->H) + c->H;
   const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
   const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
   const int64_t total_splits = pts_pad / k_split;
@@ -125,9 +126,9 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
   int64_t base = 0;
   const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
   for (int l = 0; l < c->L; ++l) {
-    const int fin = (l == 0) ? c->IN : c->H;
     p->h_base[l] = base;
-    base += (p->chunk_points / 32) * (fin / vpc2) * 64;
+    // layer 1: one 16-byte chunk of coordinates per point
+    base += l == 0 ? p->chunk_points : (p->chunk_points / 32) * (c->H / vpc2) * 64;
     p->d_base[l] = base;
     base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
   }
@@ -217,6 +218,8 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       w.stash = p.stash;
       w.d_base = p.d_base[l];
       w.h_base = p.h_base[l];
+      w.coords = l == 0;
+      w.Bmat = c->d_B;
       w.wpart = p.wpart;
       w.split_base = ch * p.splits_per_chunk;
       w.nh = c->nh;

@@ -100,6 +100,9 @@ struct WgArgs {
   int64_t kb;                  // 32-point blocks per split
   const void* stash;
   int64_t d_base, h_base;      // chunk offsets of this layer's delta / h blocks
+  int coords;                  // h blocks hold point coordinates (layer 1): the
+                               // encoding is re-derived with Bmat
+  const float4* Bmat;          // [FI/2] GRFF rows (t, z, y, x)
   float* wpart;                // [splits][nh]
   int64_t split_base, nh;
   int64_t w_off, b_off;

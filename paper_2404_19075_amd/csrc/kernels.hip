@@ -260,11 +260,20 @@ __device__ inline void sincos_rev(float f, float* s, float* c) {
   }
 }
 
+// Phase u = b . (t, z, y, x) of one GRFF row at a normalised point, reduced
+// to [-1/2, 1/2] revolutions (App. B item 2).  The forward and the layer-1
+// weight gradient both evaluate the encoding through this function, so the
+// gradient sees the very values the forward used.
+__device__ inline float grff_phase(float4 b, float rt, float rz, float ry, float rx) {
+  const float u = b.x * rt + b.y * rz + b.z * ry + b.w * rx;
+  return u - rintf(u);
+}
+
 // ---- weight panels in LDS
 //
 // Every layer's packed fragments are streamed through two LDS buffers of
 // PANEL_BYTES in "panels" of OBP output blocks: while the wave computes one
-// panel, the workgroup's global->LDS DMA (global_load_lds_dwordx4) fills the
+// panel, the workgroup's global->LDS DMA (buffer loads with the LDS bit) fills the
 // other with the next panel of the sequence (the next layer's first panel at
 // the end of a layer, the first layer of the next tile at the end of a tile).
 // One barrier per panel: after it, the panel just waited for is visible to
@@ -529,8 +538,7 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     if (ob % OBP == 0) {
       const int pi = ob / OBP;
       // the panel DMA'd last is complete; stores issued after it may still drain
-      // (every layer of a call stashes or none does, so a null stash here
-      // means the previous layer issued no stores either)
+      // (a layer without a stash simply waits for everything outstanding)
       if (stash) {
         if (pi == 0) wait_vm<VM_ENTRY>();
         else wait_vm<NB * SPP>();
@@ -682,6 +690,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
     float wgt[NB];
     chunk_t x0[NB][CI];
     // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
+    const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
@@ -744,14 +753,20 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         poff[nb] = (int)(a.off[lo] - t * TILE);
         wgt[nb] = rr.wgt;
       }
+      if (BWD_PART && hf == 0) {
+        // the layer-1 weight gradient re-derives this point's encoding from
+        // its coordinates (16 bytes instead of 2C features); padding points
+        // store zeros, which encode to finite values
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 r4 = {rt, rz, ry, rx};
+        __builtin_nontemporal_store(r4, (f4*)a.stash + a.h_base[0] + (blk0 + nb) * 32 + pl);
+      }
 #pragma unroll
       for (int c = 0; c < CI / 2; ++c) {
         float cv[VPC], sv[VPC];
 #pragma unroll
         for (int e = 0; e < VPC; ++e) {
-          const float4 b = sB[z + feat(VPC * c + e, hf)];
-          const float u = b.x * rt + b.y * rz + b.z * ry + b.w * rx;
-          const float f = u - rintf(u);
+          const float f = grff_phase(sB[z + feat(VPC * c + e, hf)], rt, rz, ry, rx);
           sincos_rev<PREC>(f, &sv[e], &cv[e]);
         }
         x0[nb][c] = T::from_f32(cv);
@@ -763,7 +778,6 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         pin(x0[nb][c + CI / 2]);
       }
     }
-    const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
     uint32_t* msk_w = &smsk[w][0][0][0];
     auto hstash = [&](int l, int ch) -> chunk_t* {
       return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
@@ -782,7 +796,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       const WSrc nx = L > 1 ? Wl(1) : after_fwd;
       const int nxb = L > 1 ? PB_H : after_fwd_bytes;
       layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
-                                           mk, hstash(0, CI), sW0, sW1, lane, w, z);
+                                           mk, nullptr, sW0, sW1, lane, w, z);
       if (BWD_PART && L > 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
@@ -795,8 +809,9 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       uint32_t mk[MSK_PER_LAYER];
       const WSrc nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
       const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
-      // stores the previous layer issued after its last DMA: its last panel's share
-      constexpr int VM_1 = BWD_PART ? NB * (CI / (H / 32 / panel_obs<CI, H>())) : 0;
+      // stores the previous layer issued after its last DMA: its last panel's
+      // share (layer 0 stores none: its input is re-derived from coordinates)
+      constexpr int VM_1 = 0;
       constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
       if (VM_1 != VM_H && l == 1)
         layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
@@ -1117,8 +1132,16 @@ __global__ __launch_bounds__(1024) void k_loss_fused(const RayRec* __restrict__ 
 // LDS into [feature][point] rows so that both matrix-core operands are read
 // as 16-byte runs of consecutive points (K = points).  The stash chunks of the
 // next iteration are loaded into registers while the current one is reduced.
-template <int PREC, int FI, int H>
-__global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
+// COORDS: the h blocks hold point coordinates (layer 1) and the encoding is
+// re-derived; otherwise they hold h_{l-1} in the register-chunk layout.
+// Threads per weight-gradient workgroup: 16 waves at H = 256 (four per SIMD,
+// each holding a quarter of the 32x32 output tiles, so that twice as many
+// stash loads are in flight per compute unit as with 8 waves), 8 below.
+template <int H>
+__host__ __device__ constexpr int wgrad_threads() { return H >= 256 ? 1024 : 512; }
+
+template <int PREC, int FI, int H, bool COORDS>
+__global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   using T = Prec<PREC>;
   using E = typename T::elem_t;
   using chunk_t = typename T::chunk_t;
@@ -1128,13 +1151,20 @@ __global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
   constexpr int CHd = chunks<PREC>(H), CHi = chunks<PREC>(FI);
   constexpr int ROW = BP + 16 / (int)sizeof(E);  // padded row (elements)
   constexpr int RB = H / 32, CB = FI / 32, NT = RB * CB;
-  constexpr int NW = 8;
+  constexpr int NTH = wgrad_threads<H>();
+  constexpr int NW = NTH / 64;
   constexpr int TPW = (NT + NW - 1) / NW;
-  constexpr int QD = NBLK * CHd * 64 / 512, QH = NBLK * CHi * 64 / 512;  // chunks per thread
-  static_assert(QD * 512 == NBLK * CHd * 64 && QH * 512 == NBLK * CHi * 64, "chunk split");
+  constexpr int QD = NBLK * CHd * 64 / NTH, QH = NBLK * CHi * 64 / NTH;  // chunks per thread
+  static_assert(QD * NTH == NBLK * CHd * 64 && QH * NTH == NBLK * CHi * 64, "chunk split");
   __shared__ __align__(16) E sD[H * ROW];
   __shared__ __align__(16) E sH[FI * ROW];
+  __shared__ float4 sBr[FI / 2];  // GRFF rows when the h blocks hold coordinates
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hf = lane >> 5;
+  constexpr int G = NTH / BP;  // threads per point when encoding coordinates
+  static_assert((FI / 2) % G == 0, "encoding rows split evenly over the point's threads");
+  constexpr bool coords = COORDS;
+  if (coords)
+    for (int k = tid; k < FI / 2; k += blockDim.x) sBr[k] = a.Bmat[k];
 
   const int64_t P = a.off[a.R];
   const int64_t n_tiles = (P + a.tile - 1) / a.tile;
@@ -1156,42 +1186,68 @@ __global__ __launch_bounds__(512) void k_wgrad(WgArgs a) {
 
   const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
   const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
+  const float4* __restrict__ Cst = (const float4*)a.stash + a.h_base;
   chunk_t cd[QD], ch[QH];
-  auto load = [&](int64_t it, chunk_t (&d)[QD], chunk_t (&h)[QH]) {
+  float4 rc;  // coordinates of point tid % BP (coordinate mode)
+  // Addresses: a uniform base per iteration plus a 32-bit per-thread byte
+  // offset (kept opaque so it is not widened into 64-bit addresses that are
+  // hoisted, spilled and reloaded between the prefetch loads).
+  const uint32_t toff = lane_off((uint32_t)tid * (uint32_t)sizeof(chunk_t));
+  auto load = [&](int64_t it, chunk_t (&d)[QD], chunk_t (&h)[QH], float4& r) {
+    const char* db = (const char*)(Dst + it * (NBLK * CHd * 64));
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
-      const int q = tid + 512 * k;
+      const int q = tid + NTH * k;
       const bool ok = it * NBLK + q / (CHd * 64) < nblk;
-      d[k] = ok ? Dst[it * (NBLK * CHd * 64) + q] : T::zero();
+      d[k] = ok ? *(const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t)) : T::zero();
     }
+    if (coords) {
+      const int p = tid % BP;
+      r = it * NBLK + p / 32 < nblk ? Cst[it * BP + p] : make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
+    const char* hb = (const char*)(Hst + it * (NBLK * CHi * 64));
 #pragma unroll
     for (int k = 0; k < QH; ++k) {
-      const int q = tid + 512 * k;
+      const int q = tid + NTH * k;
       const bool ok = it * NBLK + q / (CHi * 64) < nblk;
-      h[k] = ok ? Hst[it * (NBLK * CHi * 64) + q] : T::zero();
+      h[k] = ok ? *(const chunk_t*)(hb + toff + NTH * k * sizeof(chunk_t)) : T::zero();
     }
   };
-  load(it0, cd, ch);
+  load(it0, cd, ch, rc);
 
   for (int64_t it = it0; it < it1; ++it) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
-      const int q = tid + 512 * k;
+      const int q = tid + NTH * k;
       const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
       const int p = bl * 32 + (l & 31);
 #pragma unroll
       for (int e = 0; e < VPC; ++e) sD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
     }
+    if (coords) {
+      // layer 1's input h_0 = [cos 2 pi u ; sin 2 pi u] re-derived exactly as
+      // the forward computed it (App. B item 2)
+      const int p = tid % BP;
+#pragma unroll 4
+      for (int j = tid / BP; j < FI / 2; j += G) {
+        float sv, cv;
+        sincos_rev<PREC>(grff_phase(sBr[j], rc.x, rc.y, rc.z, rc.w), &sv, &cv);
+        sH[j * ROW + p] = (E)cv;
+        sH[(FI / 2 + j) * ROW + p] = (E)sv;
+      }
+    } else {
 #pragma unroll
-    for (int k = 0; k < QH; ++k) {
-      const int q = tid + 512 * k;
-      const int bl = q / (CHi * 64), c = (q / 64) % CHi, l = q & 63;
-      const int p = bl * 32 + (l & 31);
+      for (int k = 0; k < QH; ++k) {
+        const int q = tid + NTH * k;
+        const int bl = q / (CHi * 64), c = (q / 64) % CHi, l = q & 63;
+        const int p = bl * 32 + (l & 31);
 #pragma unroll
-      for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
+        for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
+      }
     }
-    if (it + 1 < it1) load(it + 1, cd, ch);
+    if (it + 1 < it1) load(it + 1, cd, ch, rc);
     __syncthreads();
     if (tid < H) {
       float sb = 0.f;
@@ -1422,20 +1478,21 @@ hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, c
   return hipGetLastError();
 }
 
-template <int PREC, int FI, int H>
+template <int PREC, int FI, int H, bool COORDS>
 static hipError_t wgrad_impl(const WgArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_wgrad<PREC, FI, H>), dim3(grid), dim3(512), 0, st, a);
+  hipLaunchKernelGGL((k_wgrad<PREC, FI, H, COORDS>), dim3(grid), dim3(wgrad_threads<H>()), 0, st,
+                     a);
   return hipGetLastError();
 }
 
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
 #define X(I, HH)                                                                  \
-  if (h == HH && fi == I)                                                         \
-    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH>(a, grid, st)          \
-                             : wgrad_impl<PREC_F32, I, HH>(a, grid, st);          \
-  if (h == HH && fi == HH)                                                        \
-    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, HH, HH>(a, grid, st)         \
-                             : wgrad_impl<PREC_F32, HH, HH>(a, grid, st);
+  if (h == HH && fi == I && a.coords)                                             \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH, true>(a, grid, st)    \
+                             : wgrad_impl<PREC_F32, I, HH, true>(a, grid, st);    \
+  if (h == HH && fi == HH && !a.coords)                                           \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, HH, HH, false>(a, grid, st)  \
+                             : wgrad_impl<PREC_F32, HH, HH, false>(a, grid, st);
   DINR_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
