@@ -189,7 +189,7 @@ def traffic_from_profile(kernel):
     return float(vals[key])
 
 
-def cpu_baseline(batch, n_rays=192):
+def cpu_baseline(batch, n_rays=1024):
     """The FP64 oracle as it stands, on a bounded ray subset of the same batch."""
     from oracle import oracle as O
     w = batch.workload
@@ -285,7 +285,7 @@ def main():
     probe = dict(mfma_registers=dinr.probe_mfma(0, 20000), mfma_lds_operand=dinr.probe_mfma(1, 20000))
     log(f"measured BF16 MFMA rate (TFLOP/s): {probe}")
     roof["measured_peak_tflops"] = probe
-    roof["frac_of_measured_peak"] = roof["achieved"] / probe["mfma_registers"]
+    roof["frac_of_measured_peak"] = roof["achieved"] / max(probe.values())
     roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
     cpu = None if args.no_cpu else cpu_baseline(batch)
