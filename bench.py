@@ -197,12 +197,38 @@ def cpu_baseline(batch, n_rays=1024):
     O.build(force=False)
     threads = O.threads()
     t0 = time.perf_counter()
-    O.step(w.geom, w.mlp, w.sampling, batch.B, batch.params, batch.idx[sub], batch.meas[sub])
+    ref = O.step(w.geom, w.mlp, w.sampling, batch.B, batch.params, batch.idx[sub], batch.meas[sub])
     dt = time.perf_counter() - t0
     samples = n_rays * w.sampling.n
     return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
                 sample=f"{n_rays} rays x {w.sampling.n} samples of the same batch, forward + "
-                       f"adjoint in FP64 ({dt:.1f} s)")
+                       f"adjoint in FP64 ({dt:.1f} s)"), ref
+
+
+def errors_vs_oracle(batch, ref, n_rays, ws_bytes):
+    """Relative error of the GPU step (BF16 and FP32) against the oracle's
+    step on the same ray subset: projections, gradient, loss."""
+    import torch
+    from paper_2404_19075_amd import dinr
+    w = batch.workload
+    loss_o, grad_o, proj_o = ref
+    out = {"rays": n_rays}
+    for name, prec in (("bf16", dinr.BF16), ("fp32", dinr.FP32)):
+        ctx = dinr.Context(w.geom, w.mlp, w.sampling, batch.B, precision=prec,
+                           workspace_bytes=ws_bytes)
+        P = torch.tensor(batch.params, device="cuda")
+        idx = torch.tensor(batch.idx[:n_rays], device="cuda")
+        meas = torch.tensor(batch.meas[:n_rays], device="cuda")
+        pr = torch.empty(n_rays, device="cuda")
+        g, _, lo, _ = ctx.step(P, idx, meas, proj=pr)
+        torch.cuda.synchronize()
+
+        def rel(a, b):
+            return float(np.linalg.norm(a.astype(np.float64) - b) / np.linalg.norm(b))
+        out[name] = dict(proj=rel(pr.cpu().numpy(), proj_o), grad=rel(g.cpu().numpy(), grad_o),
+                         loss=abs(float(lo.item()) - loss_o) / loss_o)
+        ctx.close()
+    return out
 
 
 def main():
@@ -288,7 +314,11 @@ def main():
     roof["frac_of_measured_peak"] = roof["achieved"] / max(probe.values())
     roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
-    cpu = None if args.no_cpu else cpu_baseline(batch)
+    cpu, vs_oracle = None, None
+    if not args.no_cpu:
+        cpu, ref = cpu_baseline(batch)
+        vs_oracle = errors_vs_oracle(batch, ref, 1024, 4 << 30)
+        log(f"errors vs the FP64 oracle on {vs_oracle['rays']} rays: {json.dumps(vs_oracle)}")
     out = {
         "metric": "ray-samples/s fwd+bwd (one training step incl. Adam), BF16 matrix cores; "
                   "p50/p99 query ms",
@@ -315,6 +345,7 @@ def main():
         "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],
         "roofline": roof,
         "cpu_baseline": cpu,
+        "vs_oracle_rel_err": vs_oracle,
         "status": status,
     }
     print(json.dumps(out), flush=True)

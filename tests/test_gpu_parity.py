@@ -240,6 +240,61 @@ def test_batch_additivity_full_c1_size():
     ctx.close()
 
 
+def test_full_size_c3_ragged_cone():
+    """The full c3 workload: 131,072 cone-beam rays with n = clamp(ceil(l/h),
+    32, 512) samples, L = 8, BF16 with the forward recomputed in the
+    backward, run as `dinr_step` runs it (two passes, several stash chunks).
+    Every ray's sample count matches the oracle's chord, 48 sampled rays'
+    projections match the oracle one by one, the loss is the FP64 mean of
+    the GPU's own residuals, and the gradient of the batch equals the sum of
+    the gradients of its halves."""
+    w = S.workload("c3")
+    b = S.make_batch(w)
+    R = len(b.idx)
+    log(f"full c3: R={R}")
+    ctx = make_ctx(w, b.B, BF16, ws_bytes=64 << 30, recompute=True)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    n = torch.empty(R, dtype=torch.int32, device="cuda")
+    proj = ctx.forward_project(P, idx, n_out=n)
+    proj2 = torch.empty(R, device="cuda")
+    g, _, loss, _ = ctx.step(P, idx, meas, proj=proj2)
+    torch.cuda.synchronize()
+    assert ctx.step_status() == 0
+    n_g = n.cpu().numpy()
+    pg = proj.cpu().numpy()
+    assert np.array_equal(pg, proj2.cpu().numpy())
+    log(f"  points {int(n_g.sum())}, n range {n_g.min()}..{n_g.max()}")
+    _, n_ref, _, ln = O.forward(w.geom, w.mlp, w.sampling, None, None, b.idx,
+                                field=(1, (0, 0, 0, 0, 0)))
+    q = ln / w.sampling.h
+    near_tie = np.abs(q - np.round(q)) < 1e-4 * np.maximum(q, 1)
+    assert np.all((n_g == n_ref) | near_tie)
+    e64 = pg.astype(np.float64) - b.meas.astype(np.float64)
+    lref = float(np.mean(e64 * e64))
+    log(f"  loss gpu {loss.item():.9e} host {lref:.9e}")
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    rng = np.random.default_rng(3)
+    pick = rng.choice(R, 48, replace=False)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx[pick],
+                             n_override=n_g[pick])
+    ep = rel(pg[pick], ref)
+    log(f"  sampled proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[BF16]
+    h = R // 2
+    g1 = ctx.project_backward(P, idx[:h].contiguous(),
+                              (2.0 / R) * (proj[:h] - meas[:h]).contiguous())
+    g2 = ctx.project_backward(P, idx[h:].contiguous(),
+                              (2.0 / R) * (proj[h:] - meas[h:]).contiguous())
+    torch.cuda.synchronize()
+    gs = g1.cpu().numpy().astype(np.float64) + g2.cpu().numpy().astype(np.float64)
+    e = rel(gs, g.cpu().numpy().astype(np.float64))
+    log(f"  additivity rel err {e:.3e}")
+    assert e <= 1e-5
+    ctx.close()
+
+
 def test_autograd_function_matches_adjoint():
     from paper_2404_19075_amd import dinr
     w = S.workload("c0")
