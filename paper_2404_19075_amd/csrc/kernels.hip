@@ -1148,6 +1148,8 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   constexpr int VPC = T::VPC;
   constexpr int NBLK = PREC == PREC_BF16 ? 2 : 1;  // 32-point blocks per iteration
   constexpr int BP = 32 * NBLK;                     // points per iteration
+  static_assert(Prec<PREC>::WAVES * Prec<PREC>::NB % (2 * NBLK) == 0,
+                "a tile holds an even number of whole iterations");
   constexpr int CHd = chunks<PREC>(H), CHi = chunks<PREC>(FI);
   constexpr int ROW = BP + 16 / (int)sizeof(E);  // padded row (elements)
   constexpr int RB = H / 32, CB = FI / 32, NT = RB * CB;
@@ -1156,8 +1158,11 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   constexpr int TPW = (NT + NW - 1) / NW;
   constexpr int QD = NBLK * CHd * 64 / NTH, QH = NBLK * CHi * 64 / NTH;  // chunks per thread
   static_assert(QD * NTH == NBLK * CHd * 64 && QH * NTH == NBLK * CHi * 64, "chunk split");
-  __shared__ __align__(16) E sD[H * ROW];
-  __shared__ __align__(16) E sH[FI * ROW];
+  // two buffer pairs of transposed operands ([feature][point] rows)
+  __shared__ __align__(16) E sD0[H * ROW];
+  __shared__ __align__(16) E sH0[FI * ROW];
+  __shared__ __align__(16) E sD1[H * ROW];
+  __shared__ __align__(16) E sH1[FI * ROW];
   __shared__ float4 sBr[FI / 2];  // GRFF rows when the h blocks hold coordinates
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hf = lane >> 5;
   constexpr int G = NTH / BP;  // threads per point when encoding coordinates
@@ -1177,6 +1182,21 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   if (it1 > nit) it1 = nit;
   if (it0 >= it1) return;
 
+  // tile k of wave w: 2 x 2 blocks of 32x32 tiles when the output divides
+  // that way (each row and column fragment then serves two tiles), else a
+  // strided walk over the tiles
+  constexpr bool BLK2 = TPW == 4 && NW * 4 == NT && RB % 2 == 0 && CB % 2 == 0;
+  auto tile_rc = [&](int k, int& rb, int& cb) -> bool {
+    if (BLK2) {
+      rb = 2 * (w / (CB / 2)) + (k >> 1);
+      cb = 2 * (w % (CB / 2)) + (k & 1);
+      return true;
+    }
+    const int tix = w + NW * k;
+    rb = tix / CB;
+    cb = tix % CB;
+    return tix < NT;
+  };
   f32x16 acc[TPW];
 #pragma unroll
   for (int k = 0; k < TPW; ++k)
@@ -1214,17 +1234,18 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
       h[k] = ok ? *(const chunk_t*)(hb + toff + NTH * k * sizeof(chunk_t)) : T::zero();
     }
   };
-  load(it0, cd, ch, rc);
-
-  for (int64_t it = it0; it < it1; ++it) {
-    __syncthreads();
+  // Transposition of the registers' iteration into one LDS buffer pair, and
+  // the weight-gradient MFMAs over the other: the two buffers alternate, so
+  // one iteration's transposition overlaps the previous one's MFMAs and each
+  // iteration needs a single barrier.
+  auto transpose = [&](E* tD, E* tH) {
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = tid + NTH * k;
       const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
       const int p = bl * 32 + (l & 31);
 #pragma unroll
-      for (int e = 0; e < VPC; ++e) sD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
+      for (int e = 0; e < VPC; ++e) tD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
     }
     if (coords) {
       // layer 1's input h_0 = [cos 2 pi u ; sin 2 pi u] re-derived exactly as
@@ -1234,8 +1255,8 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
       for (int j = tid / BP; j < FI / 2; j += G) {
         float sv, cv;
         sincos_rev<PREC>(grff_phase(sBr[j], rc.x, rc.y, rc.z, rc.w), &sv, &cv);
-        sH[j * ROW + p] = (E)cv;
-        sH[(FI / 2 + j) * ROW + p] = (E)sv;
+        tH[j * ROW + p] = (E)cv;
+        tH[(FI / 2 + j) * ROW + p] = (E)sv;
       }
     } else {
 #pragma unroll
@@ -1244,49 +1265,60 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
         const int bl = q / (CHi * 64), c = (q / 64) % CHi, l = q & 63;
         const int p = bl * 32 + (l & 31);
 #pragma unroll
-        for (int e = 0; e < VPC; ++e) sH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
+        for (int e = 0; e < VPC; ++e) tH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
       }
     }
-    if (it + 1 < it1) load(it + 1, cd, ch, rc);
-    __syncthreads();
+  };
+  auto contract = [&](const E* tD, const E* tH) {
     if (tid < H) {
       float sb = 0.f;
 #pragma unroll
-      for (int p = 0; p < BP; ++p) sb += (float)sD[tid * ROW + p];
+      for (int p = 0; p < BP; ++p) sb += (float)tD[tid * ROW + p];
       dbacc += sb;
     }
+    // K-step outer, tiles inner: a wave's tiles share their row and column
+    // fragments (2 x 2 blocks), which are read from LDS once per step
+    constexpr int KS = PREC == PREC_BF16 ? BP / 16 : 4;
 #pragma unroll
-    for (int k = 0; k < TPW; ++k) {
-      const int tix = w + NW * k;
-      if (tix < NT) {
-        const int rb = tix / CB, cb = tix % CB;
-        const E* ra = sD + (32 * rb + (lane & 31)) * ROW;
-        const E* rbp = sH + (32 * cb + (lane & 31)) * ROW;
-        if (PREC == PREC_BF16) {
+    for (int st = 0; st < KS; ++st) {
 #pragma unroll
-          for (int st = 0; st < BP / 16; ++st) {
-            const chunk_t av = *(const chunk_t*)(ra + 16 * st + 8 * hf);
-            const chunk_t bv = *(const chunk_t*)(rbp + 16 * st + 8 * hf);
-            T::mma(acc[k], av, bv);
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const chunk_t av = *(const chunk_t*)(ra + 16 * hf + 4 * q);
-            const chunk_t bv = *(const chunk_t*)(rbp + 16 * hf + 4 * q);
-            T::mma(acc[k], av, bv);
-          }
+      for (int k = 0; k < TPW; ++k) {
+        int rb, cb;
+        if (tile_rc(k, rb, cb)) {
+          const E* ra = tD + (32 * rb + (lane & 31)) * ROW;
+          const E* rbp = tH + (32 * cb + (lane & 31)) * ROW;
+          const int o = PREC == PREC_BF16 ? 16 * st + 8 * hf : 16 * hf + 4 * st;
+          T::mma(acc[k], *(const chunk_t*)(ra + o), *(const chunk_t*)(rbp + o));
         }
       }
     }
+  };
+  auto clamp_it = [&](int64_t i) { return i < it1 ? i : it1 - 1; };
+  load(it0, cd, ch, rc);
+  transpose(sD0, sH0);
+  load(clamp_it(it0 + 1), cd, ch, rc);
+  __syncthreads();
+  // a split's iteration count is even (whole tiles of an even number of
+  // iterations, splits of a.kb / NBLK iterations), so the buffers alternate
+  // in a fixed pattern
+  for (int64_t it = it0; it < it1; it += 2) {
+    transpose(sD1, sH1);  // iteration it + 1 (always within the split)
+    load(clamp_it(it + 2), cd, ch, rc);
+    contract(sD0, sH0);  // iteration it
+    __syncthreads();
+    if (it + 2 < it1) {
+      transpose(sD0, sH0);  // iteration it + 2
+      load(clamp_it(it + 3), cd, ch, rc);
+    }
+    contract(sD1, sH1);  // iteration it + 1
+    __syncthreads();
   }
   // partial row of this split: same layout as the hidden part of the gradient
   float* out = a.wpart + (a.split_base + blockIdx.x) * a.nh;
 #pragma unroll
   for (int k = 0; k < TPW; ++k) {
-    const int tix = w + NW * k;
-    if (tix < NT) {
-      const int rb = tix / CB, cb = tix % CB;
+    int rb, cb;
+    if (tile_rc(k, rb, cb)) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
