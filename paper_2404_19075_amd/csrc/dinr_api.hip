@@ -50,7 +50,7 @@ struct Plan {
   // adjoint
   void* stash = nullptr;
   int64_t chunk_points = 0, n_chunks = 0, kb = 0, splits_per_chunk = 0;
-  int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS];
+  int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS], a_base[MAX_LAYERS];
   float* wpart = nullptr;
   float* opart = nullptr;
   double* lpart = nullptr;
@@ -95,6 +95,8 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
   int64_t per_point = 0;  // stash elements per point
   // layer 1's input is stashed as the point's 4 coordinates (16 bytes)
   for (int l = 0; l < c->L; ++l) per_point += (l == 0 ? 16 / (int)esize(c->prec) : c->H) + c->H;
+  // Swish: the activation derivative of every hidden output as well
+  if (c->mlp.act == DINR_SWISH) per_point += (int64_t)c->L * c->H;
   const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
   const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
   const int64_t total_splits = pts_pad / k_split;
@@ -132,6 +134,10 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
     p->d_base[l] = base;
     base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
   }
+  for (int l = 0; l < c->L; ++l) {
+    p->a_base[l] = base;
+    if (c->mlp.act == DINR_SWISH) base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
+  }
   return DINR_OK;
 }
 
@@ -156,6 +162,7 @@ static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
   a.wtpk_bytes = p.pk.n_wt * (int64_t)esize(c->prec);
   a.L = c->L;
   a.out_act = c->mlp.out_act;
+  a.act = c->mlp.act == DINR_SWISH ? 1 : 0;
   a.tile_begin = 0;
   a.tile_end = p.n_tiles_max;
   a.part = p.part;
@@ -201,6 +208,7 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
     for (int l = 0; l < c->L; ++l) {
       a.h_base[l] = p.h_base[l];
       a.d_base[l] = p.d_base[l];
+      a.a_base[l] = p.a_base[l];
     }
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
     {
@@ -291,7 +299,7 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
     const int IN = 2 * m->n_freq, H = m->width;
     if (!shape_supported(IN, H)) { rc = bad("unsupported (2C, H): supported (128,64), (256,256)"); break; }
     if (m->depth < 1 || m->depth > MAX_LAYERS) { rc = bad("depth must be in [1, 10]"); break; }
-    if (m->act != DINR_RELU) { rc = bad("only ReLU hidden activations are implemented"); break; }
+    if (m->act != DINR_RELU && m->act != DINR_SWISH) { rc = bad("act"); break; }
     if (m->out_act != DINR_OUT_IDENTITY && m->out_act != DINR_OUT_SOFTPLUS) { rc = bad("out_act"); break; }
     if (m->precision != DINR_FP32 && m->precision != DINR_BF16) { rc = bad("precision"); break; }
     if (!std::isfinite(m->mu0)) { rc = bad("mu0"); break; }
@@ -519,7 +527,9 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   float* proj = proj_out ? proj_out : p.proj;
-  const bool fused = !c->mlp.recompute && c->samp.mode == 0 && c->tile % c->samp.n == 0;
+  // the one-pass kernel exists for ReLU networks only
+  const bool fused = !c->mlp.recompute && c->mlp.act == DINR_RELU && c->samp.mode == 0 &&
+                     c->tile % c->samp.n == 0;
   if (fused) {
     HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
                           p.tr0, st));

@@ -72,6 +72,7 @@ struct MlpArgs {
   int64_t wtpk_off[MAX_LAYERS];
   int64_t wpk_bytes, wtpk_bytes;  // sizes of the packed weight arrays
   int L, out_act;
+  int act;                          // hidden activation: 0 ReLU, 1 Swish
   int64_t tile_begin, tile_end;
   // forward outputs
   float* part;               // [2 n_tiles] partial ray-sums
@@ -81,6 +82,7 @@ struct MlpArgs {
   void* stash;
   int64_t h_base[MAX_LAYERS];  // chunk (16 B) offsets of h_l blocks
   int64_t d_base[MAX_LAYERS];  // chunk offsets of delta_l blocks
+  int64_t a_base[MAX_LAYERS];  // chunk offsets of the Swish derivatives of h_l
   float* opart;              // [grid][H+1] output-layer gradient partials
   // fused mode
   const float* meas;         // [R] measured projections

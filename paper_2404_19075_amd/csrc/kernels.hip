@@ -384,7 +384,12 @@ __device__ inline void wait_vm() {
 //   EPI_RELU:      y = relu(W x + b)
 //   EPI_RELU_MASK: the same, and the ReLU mask bits go to msk
 //   EPI_MASK:      y = (W x) . mask, the mask bits coming from msk
-enum { EPI_RELU = 0, EPI_RELU_MASK = 1, EPI_MASK = 2 };
+//   EPI_SWISH:     y = swish(W x + b) = z sigmoid(z)
+//   EPI_SWISH_D:   the same, and swish'(z) goes to the derivative stash
+//   EPI_DERIV:     y = (W x) . swish'(z), the derivatives read back from it
+enum { EPI_RELU = 0, EPI_RELU_MASK = 1, EPI_MASK = 2, EPI_SWISH = 3, EPI_SWISH_D = 4,
+       EPI_DERIV = 5 };
+__host__ __device__ constexpr bool epi_forward(int e) { return e != EPI_MASK && e != EPI_DERIV; }
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // Packed 16-bit integer max/min/multiply as single instructions (written out:
@@ -423,12 +428,37 @@ __device__ inline uint32_t neg_u32(uint32_t x) {
 template <int PREC, int H, int EPI>
 __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, int k,
                                  typename Prec<PREC>::chunk_t (&y)[Prec<PREC>::NB][chunks<PREC>(H)],
-                                 uint32_t (&msk)[mask_words<PREC, H>()]) {
+                                 uint32_t (&msk)[mask_words<PREC, H>()],
+                                 typename Prec<PREC>::chunk_t* __restrict__ actp,
+                                 const typename Prec<PREC>::chunk_t* actv, int lane) {
   using T = Prec<PREC>;
   constexpr int VPC = T::VPC, CPO = 16 / VPC, OB = H / 32;
   const int nb = k / CPO, kk = k % CPO;
   const int g = nb * OB + ob;
   const int mw = g >> 1;
+  if constexpr (EPI == EPI_SWISH || EPI == EPI_SWISH_D) {
+    // swish(z) = z s and swish'(z) = s (1 + z (1 - s)), s = sigmoid(z)
+    // (App. B item 3); derivatives of the outputs go to the stash, rounded
+    // like the operands
+    float v[VPC], dv[VPC];
+#pragma unroll
+    for (int e = 0; e < VPC; ++e) {
+      const float zz = acc[nb][kk * VPC + e];
+      const float sg = __frcp_rn(1.0f + __expf(-zz));
+      v[e] = zz * sg;
+      dv[e] = sg * (1.0f + zz * (1.0f - sg));
+    }
+    y[nb][ob * CPO + kk] = T::from_f32(v);
+    if (EPI == EPI_SWISH_D)
+      T::store_nt(&actp[(nb * chunks<PREC>(H) + ob * CPO + kk) * 64 + lane], T::from_f32(dv));
+    return;
+  } else if constexpr (EPI == EPI_DERIV) {
+    float v[VPC];
+#pragma unroll
+    for (int e = 0; e < VPC; ++e) v[e] = acc[nb][kk * VPC + e] * T::get(actv[k], e);
+    y[nb][ob * CPO + kk] = T::from_f32(v);
+    return;
+  }
   if constexpr (PREC == PREC_BF16) {
     // Round first, then work on the bf16 pairs, two values per register:
     // ReLU is max_i16 of the bit patterns (negative values are negative
@@ -512,7 +542,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
                              WSrc gbias_next, float* sbias_next,
                              uint32_t (&msk)[mask_words<PREC, H>()],
                              typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW0, char* sW1,
-                             int lane, int w, int z) {
+                             int lane, int w, int z,
+                             typename Prec<PREC>::chunk_t* __restrict__ actp = nullptr) {
   using T = Prec<PREC>;
   using chunk_t = typename T::chunk_t;
   constexpr int NB = T::NB, VPC = T::VPC;
@@ -533,6 +564,7 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 #pragma unroll
     for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
   f32x16 accp[NB];
+  chunk_t act_cur[NEPI], act_nxt[NEPI];  // EPI_DERIV: derivative chunks (blocks ob-1, ob)
 #pragma unroll
   for (int ob = 0; ob < OB; ++ob) {
     if (ob % OBP == 0) {
@@ -565,8 +597,17 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     }
     const chunk_t* __restrict__ Wp =
         (const chunk_t*)(((ob / OBP) & 1) ? sW1 : sW0) + (ob % OBP) * KC * 64;
+    if (EPI == EPI_DERIV) {
+      // derivatives of this block's outputs, used by its epilogue during the
+      // next block (one block of latency to hide)
+      const char* ap = (const char*)actp + lane_off((uint32_t)(lane * sizeof(chunk_t)));
+#pragma unroll
+      for (int k = 0; k < NEPI; ++k)
+        act_nxt[k] = *(const chunk_t*)(ap + ((k / CPO) * chunks<PREC>(H) + ob * CPO + k % CPO) *
+                                                64 * sizeof(chunk_t));
+    }
     f32x16 acc[NB];
-    if (EPI != EPI_MASK) {
+    if (epi_forward(EPI)) {
       float bq[16];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -586,8 +627,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     chunk_t a[D + 1];
 #pragma unroll
     for (int c = 0; c < D && c < KC; ++c) a[c] = Wp[c * 64 + lane];
-    // the bias reads (not EPI_MASK) and the first D fragment reads lead the block
-    __builtin_amdgcn_sched_group_barrier(0x100, (D < KC ? D : KC) + (EPI != EPI_MASK ? 4 : 0),
+    // the bias reads (forward kinds) and the first D fragment reads lead the block
+    __builtin_amdgcn_sched_group_barrier(0x100, (D < KC ? D : KC) + (epi_forward(EPI) ? 4 : 0),
                                          0);
 #pragma unroll
     for (int c = 0; c < KC; ++c) {
@@ -600,17 +641,23 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
         // epilogue chunks of block ob-1 assigned to this step
 #pragma unroll
         for (int k = 0; k < NEPI; ++k)
-          if ((k * KC) / NEPI == c) epi_chunk<PREC, H, EPI>(accp, ob - 1, k, y, msk);
+          if ((k * KC) / NEPI == c)
+            epi_chunk<PREC, H, EPI>(accp, ob - 1, k, y, msk, actp, act_cur, lane);
       }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) accp[nb] = acc[nb];
+    if (EPI == EPI_DERIV)
+#pragma unroll
+      for (int k = 0; k < NEPI; ++k) act_cur[k] = act_nxt[k];
   }
 #pragma unroll
-  for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk);
+  for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk, actp, act_cur, lane);
 }
 
-template <int PREC, int IN, int H, int MODE>
+// ACT: 0 ReLU hidden layers, 1 Swish (derivatives of every layer go through
+// a stash in the adjoint modes; the one-pass fused mode is ReLU only)
+template <int PREC, int IN, int H, int MODE, int ACT>
 __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   using T = Prec<PREC>;
   using chunk_t = typename T::chunk_t;
@@ -620,7 +667,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   constexpr int TILE = WAVES_PER_WG * NB * 32;
   constexpr int C = IN / 2;
   constexpr int MSK_PER_LAYER = mask_words<PREC, H>();  // 32-bit mask words per lane per layer
-  constexpr int MSK_LAYERS = (MODE != MODE_FWD) ? MAX_LAYERS - 1 : 1;
+  constexpr int MSK_LAYERS = (MODE != MODE_FWD && ACT == 0) ? MAX_LAYERS - 1 : 1;
   constexpr int PB_IN = panel_bytes<CI, H>(), PB_H = panel_bytes<CHh, H>();
   // the wave index in a scalar register: every address derived from it
   // (stash blocks, LDS slices, DMA destinations) is then wave-uniform too
@@ -655,8 +702,12 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   const int L = a.L;
   constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED || MODE == MODE_QUERY;
   constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
-  // the adjoint needs the ReLU masks of the forward layers
-  constexpr int FWD_EPI = BWD_PART ? EPI_RELU_MASK : EPI_RELU;
+  // the adjoint needs the ReLU masks (or the Swish derivatives) of the
+  // forward layers
+  static_assert(ACT == 0 || MODE != MODE_FUSED, "the fused one-pass mode is ReLU only");
+  constexpr int FWD_EPI = ACT == 1 ? (BWD_PART ? EPI_SWISH_D : EPI_SWISH)
+                                   : (BWD_PART ? EPI_RELU_MASK : EPI_RELU);
+  constexpr int ADJ_EPI = ACT == 1 ? EPI_DERIV : EPI_MASK;
   double lossacc = 0.0;
   const float g_scale = 2.0f / (float)a.R;
   const __amdgpu_buffer_rsrc_t rW = buffer_rsrc(a.Wpk, a.wpk_bytes);
@@ -779,6 +830,11 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       }
     }
     uint32_t* msk_w = &smsk[w][0][0][0];
+    // Swish derivatives of layer l's outputs, in the layout of the stash
+    auto astash = [&](int l) -> chunk_t* {
+      return (BWD_PART && ACT == 1) ? (chunk_t*)a.stash + a.a_base[l] + blk0 * (CHh * 64)
+                                    : nullptr;
+    };
     auto hstash = [&](int l, int ch) -> chunk_t* {
       return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
     };
@@ -796,8 +852,8 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       const WSrc nx = L > 1 ? Wl(1) : after_fwd;
       const int nxb = L > 1 ? PB_H : after_fwd_bytes;
       layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
-                                           mk, nullptr, sW0, sW1, lane, w, z);
-      if (BWD_PART && L > 1)
+                                           mk, nullptr, sW0, sW1, lane, w, z, astash(0));
+      if (BWD_PART && ACT == 0 && L > 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     }
@@ -815,11 +871,11 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
       if (VM_1 != VM_H && l == 1)
         layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
-                                                 hstash(l, CHh), sW0, sW1, lane, w, z);
+                                                 hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
       else
         layer<PREC, CHh, H, FWD_EPI, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
-                                                 hstash(l, CHh), sW0, sW1, lane, w, z);
-      if (BWD_PART && l < L - 1)
+                                                 hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
+      if (BWD_PART && ACT == 0 && l < L - 1)
 #pragma unroll
         for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
     };
@@ -963,8 +1019,18 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
         if (lane == 0) sdwo[w][H] += sb;
       }
-      // delta_L = w_o dob . relu'(z_L)
+      // delta_L = w_o dob . act'(z_L)
       chunk_t d[NB][CHh];
+      if (ACT == 1) {
+        // Swish: the last layer's derivatives, just stored by this wave
+        wait_vm<0>();
+        const char* ap = (const char*)astash(L - 1) + lane_off((uint32_t)(lane * sizeof(chunk_t)));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int c = 0; c < CHh; ++c)
+            d[nb][c] = *(const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t));
+      }
 #pragma unroll
       for (int c = 0; c < CHh; ++c) {
         float wv[VPC];
@@ -973,12 +1039,17 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
           float v[VPC];
+          if (ACT == 1) {
 #pragma unroll
-          for (int e = 0; e < VPC; ++e) {
-            // h_L >= 0 (ReLU output): h > 0 iff its bit pattern is non-zero
-            const int hb = __float_as_int(T::get(y[nb][c], e));
-            const int keep = (int)neg_u32((uint32_t)hb) >> 31;  // 0 or all ones
-            v[e] = __int_as_float(__float_as_int(wv[e] * dob[nb]) & keep);
+            for (int e = 0; e < VPC; ++e) v[e] = (wv[e] * dob[nb]) * T::get(d[nb][c], e);
+          } else {
+#pragma unroll
+            for (int e = 0; e < VPC; ++e) {
+              // h_L >= 0 (ReLU output): h > 0 iff its bit pattern is non-zero
+              const int hb = __float_as_int(T::get(y[nb][c], e));
+              const int keep = (int)neg_u32((uint32_t)hb) >> 31;  // 0 or all ones
+              v[e] = __int_as_float(__float_as_int(wv[e] * dob[nb]) & keep);
+            }
           }
           d[nb][c] = T::from_f32(v);
         }
@@ -996,14 +1067,17 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       // iteration with swapped roles, as in the forward.
       auto adj = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
         uint32_t mk[MSK_PER_LAYER];
+        if (ACT == 0)
 #pragma unroll
-        for (int k = 0; k < MSK_PER_LAYER; ++k) mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
+          for (int k = 0; k < MSK_PER_LAYER; ++k)
+            mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
         const WSrc nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : none);
         const int nxb = l > 1 ? PB_H : PB_IN;
         // entering from the forward's last layer or from the previous adjoint
         // layer: both stored their last panel's share of a width-H input
-        layer<PREC, CHh, H, EPI_MASK, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
-            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z);
+        layer<PREC, CHh, H, ADJ_EPI, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
+            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z,
+            astash(l - 1));
       };
       for (int l = L - 1; l >= 1; l -= 2) {
         chunk_t t2[NB][CHh];
@@ -1449,15 +1523,18 @@ hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* 
 
 template <int PREC, int IN, int H>
 static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st) {
-  if (mode == MODE_FWD)
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
-                       st, a);
+  const dim3 b(Prec<PREC>::WAVES * 64);
+  if (mode == MODE_FUSED && a.act != 0) return hipErrorInvalidValue;
+  if (mode == MODE_FWD && a.act == 0)
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD, 0>), dim3(grid), b, 0, st, a);
+  else if (mode == MODE_FWD)
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD, 1>), dim3(grid), b, 0, st, a);
+  else if (mode == MODE_BWD && a.act == 0)
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD, 0>), dim3(grid), b, 0, st, a);
   else if (mode == MODE_BWD)
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
-                       st, a);
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD, 1>), dim3(grid), b, 0, st, a);
   else
-    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED>), dim3(grid), dim3(Prec<PREC>::WAVES * 64),
-                       0, st, a);
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED, 0>), dim3(grid), b, 0, st, a);
   return hipGetLastError();
 }
 
@@ -1474,8 +1551,12 @@ hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int g
 
 template <int PREC, int IN, int H>
 static hipError_t query_impl(const MlpArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_QUERY>), dim3(grid), dim3(Prec<PREC>::WAVES * 64), 0,
-                     st, a);
+  if (a.act == 0)
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_QUERY, 0>), dim3(grid), dim3(Prec<PREC>::WAVES * 64),
+                       0, st, a);
+  else
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_QUERY, 1>), dim3(grid), dim3(Prec<PREC>::WAVES * 64),
+                       0, st, a);
   return hipGetLastError();
 }
 

@@ -226,6 +226,7 @@ static void scheduler(dinr_server* s) {
     a.wtpk_bytes = s->pk.n_wt * (int64_t)esize(c->prec);
     a.L = c->L;
     a.out_act = c->mlp.out_act;
+    a.act = c->mlp.act == DINR_SWISH ? 1 : 0;
     a.qdesc = s->d_desc;
     a.qtiles = b.d_tiles;
     a.n_qtiles = n;

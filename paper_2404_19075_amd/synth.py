@@ -157,8 +157,9 @@ def _views(n_views: int, span: float) -> tuple:
 
 
 def workload(name: str) -> Workload:
-    """The five workloads: c0 tiny parity case, c1 FP32 parallel beam, c2 the
-    same in BF16, c3 ragged cone beam, c4 serving (weights as c2)."""
+    """The workloads: c0 tiny parity case, c1 FP32 parallel beam, c2 the same
+    in BF16, c3 ragged cone beam, c4 serving (weights as c2), and "paper", the
+    paper's own Swish network on the c2 geometry."""
     if name == "c0":
         th, tt = _views(90, math.pi)
         g = Geometry(kind=0, rows=32, cols=32, n_views=90, pitch_u=3.0 / 32, pitch_v=3.0 / 32,
@@ -188,6 +189,14 @@ def workload(name: str) -> Workload:
                         n_ellipsoids=20, centre_range=0.4, max_speed=0.2,
                         axes_range=(0.05, 0.3), kappa_range=0.3, rotate=True, noise=0.01,
                         precision="bf16", recompute=True, seed=1003)
+    if name == "paper":
+        # the network of Appendix B (Swish hidden layers, linear output,
+        # 2C = H = 256, five hidden layers, sigma_s = 0.5, sigma_t = 0.1) on the
+        # c2 geometry and batch
+        w = workload("c2")
+        return dataclasses.replace(
+            w, name="paper", mlp=MLPSpec(n_freq=128, width=256, depth=5, act=1, out_act=0,
+                                         sigma_t=0.1, sigma_s=0.5), seed=1005)
     raise KeyError(name)
 
 

@@ -72,7 +72,7 @@ def _replace(obj, **kw):
     dict(mlp=dict(width=96)),
     dict(mlp=dict(depth=0)),
     dict(mlp=dict(depth=11)),
-    dict(mlp=dict(act=1)),
+    dict(mlp=dict(act=2)),
     dict(mlp=dict(out_act=5)),
     dict(samp=dict(n=0)),
     dict(samp=dict(mode=1, h=0.0)),

@@ -328,3 +328,55 @@ def test_fused_pass_matches_recompute_pass(name, R):
     assert np.array_equal(o1["proj"], o2["proj"])
     assert rel(o1["grad"], o2["grad"]) <= 1e-6
     assert abs(o1["loss"] - o2["loss"]) <= 1e-12 * o2["loss"]
+
+
+def swish_c0():
+    """c0 with the paper's hidden activation and output (Swish, linear)."""
+    w = S.workload("c0")
+    return dataclasses.replace(w, mlp=dataclasses.replace(w.mlp, act=1, out_act=0))
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_swish_c0_step(prec):
+    """Swish hidden layers (Appendix B item 3) through the two-pass step: the
+    forward kernel, then the backward kernel that stashes swish'(z) of every
+    layer for the adjoint chain."""
+    w = swish_c0()
+    b = S.make_batch(w)
+    log(f"test_swish_c0_step prec={prec}")
+    proj_f, n = run_forward(w, b, prec)
+    out = run_step(w, b, prec)
+    loss, grad, proj = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas)
+    ep, ef = rel(out["proj"], proj), rel(proj_f, proj)
+    el = abs(out["loss"] - loss) / loss
+    log(f"  proj {ep:.3e} forward {ef:.3e} loss {el:.3e}")
+    assert ep <= TOL_PROJ[prec] and ef <= TOL_PROJ[prec]
+    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"swish c0 prec={prec}")
+    assert out["status"] == 0
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_paper_swish_network_ray_subset(prec):
+    """The paper's network (2C = H = 256, five Swish layers, linear output,
+    sigma_s = 0.5, sigma_t = 0.1) on 160 rays of the c2 geometry."""
+    w = small_workload("paper", 160)
+    b = S.make_batch(w)
+    log(f"test_paper_swish_network_ray_subset prec={prec}")
+    out = run_step(w, b, prec)
+    loss, grad, proj = oracle_step("paper-160", w, b)
+    ep = rel(out["proj"], proj)
+    log(f"  proj {ep:.3e} loss gpu {out['loss']:.6e} oracle {loss:.6e}")
+    assert ep <= TOL_PROJ[prec]
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"paper prec={prec}")
+
+
+def test_swish_recompute_flag_is_the_same_step():
+    """Swish networks always take the two-pass route: the recompute flag
+    changes nothing, bit for bit."""
+    w = small_workload("paper", 160)
+    b = S.make_batch(w)
+    o1 = run_step(w, b, BF16)
+    o2 = run_step(w, b, BF16, recompute=True)
+    assert np.array_equal(o1["proj"], o2["proj"])
+    assert np.array_equal(o1["grad"], o2["grad"])

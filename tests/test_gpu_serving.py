@@ -162,3 +162,24 @@ def test_admission_by_memory_budget():
         assert torch.equal(ref, o)
     srv.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_swish_slice_matches_oracle_field(prec):
+    """Queries of a Swish network (the paper's activation) through the server."""
+    from paper_2404_19075_amd import dinr
+    w0 = S.workload("c0")
+    w = dataclasses.replace(w0, mlp=dataclasses.replace(w0.mlp, act=1, out_act=0))
+    b = S.make_batch(w, n_rays=8)
+    ctx, P, srv = server_for(w, b, prec)
+    n, z, t = 40, -0.21, 0.61
+    out = torch.empty(n * n, device="cuda")
+    tk = srv.submit(dinr.QUERY_SLICE, n, z, t, out)
+    srv.wait(tk)
+    got = out.cpu().numpy()
+    ref = O.field_points(w.geom, w.mlp, b.B, b.params, slice_points(w.geom, n, z, t))
+    e = rel(got, ref)
+    log(f"  swish slice prec={prec} rel err {e:.3e}")
+    assert e <= TOL[prec]
+    srv.close()
+    ctx.close()
