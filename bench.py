@@ -231,6 +231,39 @@ def errors_vs_oracle(batch, ref, n_rays, ws_bytes):
     return out
 
 
+def alg_flops(spec, P_pts):
+    """Algorithmic FLOP per step of each kernel class: the forward GEMMs, the
+    adjoint's input-gradient GEMMs (a recomputing backward kernel's repeat of
+    the forward is not counted), the weight-gradient GEMMs."""
+    f_fwd = spec.fwd_flops_per_point()
+    shapes = spec.layer_shapes()
+    f_dx = sum(2 * o * i for o, i in shapes[1:])
+    f_dw = sum(2 * o * i for o, i in shapes[:-1])
+    return {"mlp_fwd": f_fwd * P_pts, "mlp_bwd": (f_dx + 2 * shapes[-1][1]) * P_pts,
+            "mlp_fused": (f_fwd + f_dx + 2 * shapes[-1][1]) * P_pts, "wgrad": f_dw * P_pts}
+
+
+def paper_network(steps, warmup, ws):
+    """The paper's own network (Swish hidden layers, linear output, five layers
+    of width 256) on a c2-sized batch: the two-pass BF16 step."""
+    from paper_2404_19075_amd import dinr
+    from paper_2404_19075_amd import synth as S
+    b = S.make_batch("paper")
+    P_pts = len(b.idx) * b.workload.sampling.n
+    ms, kern, _, status, _ = run_workload("paper", dinr.BF16, b, steps, warmup, ws)
+    alg = alg_flops(b.workload.mlp, P_pts)
+    out = dict(workload="paper network on the c2 geometry: 65536 rays x 256 samples, GRFF "
+                        "2C=256 (sigma_s 0.5, sigma_t 0.1), 5 Swish layers of width 256, "
+                        "linear output, BF16 MLP GEMMs",
+               ms_per_step=ms, value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
+               step_tflops=b.workload.mlp.flops_per_point() * P_pts / (ms * 1e-3) / 1e12,
+               kernels={k: dict(ms_per_step=v["ms_per_step"],
+                                alg_tflops=alg[k] / (v["ms_per_step"] * 1e-3) / 1e12)
+                        for k, v in kern.items()})
+    log(f"paper network step {ms:.3f} ms  {json.dumps(out['kernels'])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +273,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--workspace-gb", type=float, default=120.0)
     ap.add_argument("--no-serving", action="store_true", help="skip the query-serving run")
+    ap.add_argument("--no-paper-net", action="store_true",
+                    help="skip the step of the paper's Swish network")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale the memory "
                          "counters of a profiler run) and exit")
@@ -288,16 +323,8 @@ def main():
                     kernels=kern32)
 
     spec = w.mlp
-    f_fwd = spec.fwd_flops_per_point()
     f_all = spec.flops_per_point()
-    shapes = spec.layer_shapes()
-    f_dx = sum(2 * o * i for o, i in shapes[1:])
-    f_dw = sum(2 * o * i for o, i in shapes[:-1])
-    # algorithmic FLOP per launch of each kernel class (per step: one launch of
-    # the forward, one backward launch per stash chunk, one wgrad launch per
-    # layer and chunk)
-    alg = {"mlp_fwd": f_fwd * P_pts, "mlp_bwd": (f_dx + 2 * shapes[-1][1]) * P_pts,
-           "mlp_fused": (f_fwd + f_dx + 2 * shapes[-1][1]) * P_pts, "wgrad": f_dw * P_pts}
+    alg = alg_flops(spec, P_pts)
     dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
     ach = alg[dom] / (kern[dom]["ms_per_step"] * 1e-3)
     roof = dict(bound="mfma", kernel=dom, achieved=ach / 1e12, peak=PEAK["bf16"] / 1e12,
@@ -314,6 +341,7 @@ def main():
     roof["frac_of_measured_peak"] = roof["achieved"] / max(probe.values())
     roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
+    paper = None if args.no_paper_net else paper_network(max(2, args.steps // 2), 1, ws)
     cpu, vs_oracle = None, None
     if not args.no_cpu:
         cpu, ref = cpu_baseline(batch)
@@ -341,6 +369,7 @@ def main():
                    "ray_samples": P_pts, "flop_per_sample": f_all},
         "fp32": fp32,
         "serving": serve,
+        "paper_network": paper,
         "p50_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p50_ms"],
         "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],
         "roofline": roof,

@@ -444,9 +444,11 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
 #pragma unroll
     for (int e = 0; e < VPC; ++e) {
       const float zz = acc[nb][kk * VPC + e];
-      const float sg = __frcp_rn(1.0f + __expf(-zz));
+      // v_rcp_f32 (1 ulp): a correctly rounded reciprocal is an IEEE
+      // division sequence five times as long
+      const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-zz));
       v[e] = zz * sg;
-      dv[e] = sg * (1.0f + zz * (1.0f - sg));
+      dv[e] = __builtin_fmaf(v[e], 1.0f - sg, sg);  // s + z s (1 - s)
     }
     y[nb][ob * CPO + kk] = T::from_f32(v);
     if (EPI == EPI_SWISH_D)
