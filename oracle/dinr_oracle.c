@@ -19,6 +19,8 @@
  *   - rotation of the source-detector pair by -theta, time t_i = T_m: Sec. II
  *   - equi-spaced samples along each ray inside the field of view, weight
  *     w = mu0 * l (chord length in the FOV): Appendix A, Eqs. (1), (2), (7)
+ *   - D x D rays per projection, one to the centre of each sub-pixel, and
+ *     pbar the average over the samples of all of them: Appendix A
  *   - coordinate normalisation to [-1,1], Gaussian random Fourier features
  *     [cos 2 pi B r ; sin 2 pi B r], FC layers, scalar output: Appendix B
  *   - squared distance, local loss, gradient: Eqs. (3), (5), (8)
@@ -32,6 +34,8 @@
  *   - mu0 is applied once, inside w; M itself excludes mu0.
  *   - hidden activation ReLU or Swish; output identity or softplus.
  *   - a ray that misses the FOV has n = 0 and prediction 0.
+ *   - with D > 1, |Phi_i| counts the samples of all D^2 rays and each sample
+ *     is weighted by the chord length of its own ray.
  *
  * Parameter layout (flat, FP64 here): for l = 1..L: W_l [H x fan_in]
  * row-major (row = output unit), b_l [H]; then w_o [H], b_o [1].
@@ -76,6 +80,8 @@ typedef struct {
   int32_t n;
   int32_t n_min, n_max;
   double h;
+  int32_t sub;      /* D: rays per projection D x D (0 is read as 1; at most 16) */
+  int32_t pad_;
 } orc_sampling;
 
 /* Analytic replacement fields used to pin the geometry and the quadrature.
@@ -94,18 +100,22 @@ typedef struct {
 
 /* ---------------------------------------------------------------- geometry */
 
-/* Ray of projection index i (Sec. II): view m = floor(i/N), pixel n = i mod N,
- * row = n / cols, col = n mod cols.  Returns 0, or -1 for an index out of
- * range.  d is a unit vector, so the ray parameter s is a length. */
-int orc_ray(const orc_geom* g, int64_t i, double o[3], double d[3], double* t) {
+/* Ray k of projection index i (Sec. II, Appendix A): view m = floor(i/N),
+ * pixel n = i mod N, row = n / cols, col = n mod cols; the pixel is divided
+ * into D x D sub-pixels and ray k = b D + a ends at the centre of sub-pixel
+ * (row b, column a).  Returns 0, or -1 for an index out of range.  d is a unit
+ * vector, so the ray parameter s is a length. */
+int orc_subray(const orc_geom* g, int64_t i, int32_t D, int32_t k, double o[3], double d[3],
+               double* t) {
   const int64_t N = (int64_t)g->rows * g->cols;
-  if (i < 0 || i >= N * g->n_views) return -1;
+  if (i < 0 || i >= N * g->n_views || D < 1 || k < 0 || k >= D * D) return -1;
   const int64_t m = i / N;
   const int64_t n = i % N;
   const int64_t row = n / g->cols;
   const int64_t col = n % g->cols;
-  const double u = ((double)col - 0.5 * (g->cols - 1)) * g->pitch_u + g->off_u;
-  const double v = ((double)row - 0.5 * (g->rows - 1)) * g->pitch_v + g->off_v;
+  const double fa = (k % D + 0.5) / D - 0.5, fb = (k / D + 0.5) / D - 0.5;
+  const double u = ((double)col + fa - 0.5 * (g->cols - 1)) * g->pitch_u + g->off_u;
+  const double v = ((double)row + fb - 0.5 * (g->rows - 1)) * g->pitch_v + g->off_v;
   double o0[3], d0[3];
   if (g->kind == 0) {
     o0[0] = 0.0; o0[1] = u; o0[2] = v;
@@ -130,6 +140,13 @@ int orc_ray(const orc_geom* g, int64_t i, double o[3], double d[3], double* t) {
   *t = g->time[m];
   return 0;
 }
+
+/* The single ray to the centre of pixel i (D = 1). */
+int orc_ray(const orc_geom* g, int64_t i, double o[3], double d[3], double* t) {
+  return orc_subray(g, i, 1, 0, o, d, t);
+}
+
+static int32_t sub_of(const orc_sampling* s) { return s->sub > 1 ? s->sub : 1; }
 
 /* Chord of the ray inside the field of view: entry parameter and length.
  * Box: slab intersection.  Cylinder about z: quadratic in x,y plus a z slab.
@@ -383,34 +400,45 @@ static int set_threads(int nthreads) {
 #endif
 }
 
-/* One ray: prediction p = (1/n) sum_j mu0 l M(r_j) (Eqs. (1), (2), (7)).
+/* One projection: the D^2 rays of its pixel with n_k samples each, and
+ * pbar = (1/|Phi|) sum_k sum_j mu0 l_k M(r_kj), |Phi| = sum_k n_k
+ * (Eqs. (1), (2), (7), Appendix A).  n_forced (nullable) holds the D^2 sample
+ * counts to use; n_used, s_in_o, len_o receive the D^2 rays' values.
  * Returns -1 on a bad index. */
 static int ray_predict(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp,
                        const orc_field* f, const double* B, const double* P, int64_t idx,
-                       int32_t n_forced, orc_ws* w, double* proj, int32_t* n_used,
+                       const int32_t* n_forced, orc_ws* w, double* proj, int32_t* n_used,
                        double* s_in_o, double* len_o) {
-  double o[3], d[3], t, s_in, len;
-  if (orc_ray(g, idx, o, d, &t) != 0) return -1;
-  orc_clip(g, o, d, &s_in, &len);
-  int32_t n = (n_forced >= 0) ? n_forced : orc_nsamp(sp, len);
-  if (!(len > 0.0)) n = 0;
-  double sum = 0.0;
-  for (int32_t j = 0; j < n; ++j) {
-    const double s = s_in + (j + 0.5) * len / n;
-    const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
-    double rbar[4], zo;
-    orc_normalize(g, x, t, rbar);
-    sum += field_eval(m, f, B, P, x, t, rbar, w, &zo);
+  const int32_t D = sub_of(sp);
+  double acc = 0.0;  /* sum over rays of l_k sum_j M */
+  int64_t n_all = 0;
+  for (int32_t k = 0; k < D * D; ++k) {
+    double o[3], d[3], t, s_in, len;
+    if (orc_subray(g, idx, D, k, o, d, &t) != 0) return -1;
+    orc_clip(g, o, d, &s_in, &len);
+    int32_t n = n_forced ? n_forced[k] : orc_nsamp(sp, len);
+    if (!(len > 0.0)) n = 0;
+    double sum = 0.0;
+    for (int32_t j = 0; j < n; ++j) {
+      const double s = s_in + (j + 0.5) * len / n;
+      const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+      double rbar[4], zo;
+      orc_normalize(g, x, t, rbar);
+      sum += field_eval(m, f, B, P, x, t, rbar, w, &zo);
+    }
+    acc += len * sum;
+    n_all += n;
+    n_used[k] = n;
+    s_in_o[k] = s_in;
+    len_o[k] = len;
   }
-  *proj = (n > 0) ? m->mu0 * len / n * sum : 0.0;
-  *n_used = n;
-  *s_in_o = s_in;
-  *len_o = len;
+  *proj = (n_all > 0) ? m->mu0 * acc / (double)n_all : 0.0;
   return 0;
 }
 
-/* Forward projection of a batch of rays.  n_override (nullable) forces the
- * per-ray sample count; proj, n_out, s_in_out, len_out are [R] (the last three
+/* Forward projection of a batch of R projections.  n_override (nullable)
+ * forces the per-ray sample counts; proj is [R]; n_override, n_out, s_in_out,
+ * len_out are [R D^2], ray k of projection r at r D^2 + k (the last three
  * nullable).  Returns 0, or -1 on a bad index or allocation failure. */
 int orc_forward(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp,
                 const orc_field* f, const double* B, const double* P, const int64_t* idx,
@@ -427,18 +455,22 @@ int orc_forward(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp,
     } else {
 #pragma omp for schedule(dynamic, 4)
       for (int64_t r = 0; r < R; ++r) {
-        double p, si, ln;
-        int32_t n;
-        if (ray_predict(g, m, sp, f, B, P, idx[r], n_override ? n_override[r] : -1, &w, &p,
-                        &n, &si, &ln) != 0) {
+        const int32_t D2 = sub_of(sp) * sub_of(sp);
+        double p, si[16 * 16], ln[16 * 16];
+        int32_t n[16 * 16];
+        if (D2 > 16 * 16 ||
+            ray_predict(g, m, sp, f, B, P, idx[r], n_override ? n_override + r * D2 : NULL,
+                        &w, &p, n, si, ln) != 0) {
 #pragma omp atomic write
           err = -1;
           continue;
         }
         proj[r] = p;
-        if (n_out) n_out[r] = n;
-        if (s_in_out) s_in_out[r] = si;
-        if (len_out) len_out[r] = ln;
+        for (int32_t k = 0; k < D2; ++k) {
+          if (n_out) n_out[r * D2 + k] = n[k];
+          if (s_in_out) s_in_out[r * D2 + k] = si[k];
+          if (len_out) len_out[r * D2 + k] = ln[k];
+        }
       }
     }
     ws_free(&w);
@@ -448,7 +480,9 @@ int orc_forward(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp,
 
 /* One training step's loss and gradient (Eqs. (3), (5), (8)) with the MLP
  * field:  L = (1/R) sum_i (p_i - pbar_i)^2,
- *         dL/dgamma = (1/R) sum_i 2 (pbar_i - p_i) (1/n_i) sum_j mu0 l_i dM_ij/dgamma.
+ *         dL/dgamma = (1/R) sum_i 2 (pbar_i - p_i) (1/|Phi_i|) sum_j mu0 l_ij dM_ij/dgamma,
+ * the samples j of projection i spanning its D^2 rays (l_ij: the chord of the
+ * ray holding sample j).  n_override (nullable) is [R D^2].
  * grad is [nparams] and is overwritten.  proj (nullable) receives pbar. */
 int orc_step(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp, const double* B,
              const double* P, const int64_t* idx, int64_t R, const double* meas,
@@ -476,37 +510,54 @@ int orc_step(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp, const 
     } else {
 #pragma omp for schedule(dynamic, 4)
       for (int64_t r = 0; r < R; ++r) {
-        double o[3], d[3], t, s_in, len;
-        if (orc_ray(g, idx[r], o, d, &t) != 0) {
+        const int32_t D = sub_of(sp), D2 = D * D;
+        /* the D^2 rays of projection r: pbar first, then the adjoint */
+        double acc = 0.0;
+        int64_t n_all = 0;
+        int bad = D2 > 16 * 16;
+        for (int32_t k = 0; k < D2 && !bad; ++k) {
+          double o[3], d[3], t, s_in, len;
+          if (orc_subray(g, idx[r], D, k, o, d, &t) != 0) { bad = 1; break; }
+          orc_clip(g, o, d, &s_in, &len);
+          int32_t n = n_override ? n_override[r * D2 + k] : orc_nsamp(sp, len);
+          if (!(len > 0.0)) n = 0;
+          double sum = 0.0;
+          for (int32_t j = 0; j < n; ++j) {
+            const double s = s_in + (j + 0.5) * len / n;
+            const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+            double rbar[4], zo;
+            orc_normalize(g, x, t, rbar);
+            sum += mlp_forward(m, B, P, rbar, &w, &zo);
+          }
+          acc += len * sum;
+          n_all += n;
+        }
+        if (bad) {
 #pragma omp atomic write
           err = -1;
           continue;
         }
-        orc_clip(g, o, d, &s_in, &len);
-        int32_t n = n_override ? n_override[r] : orc_nsamp(sp, len);
-        if (!(len > 0.0)) n = 0;
-        double sum = 0.0;
-        for (int32_t j = 0; j < n; ++j) {
-          const double s = s_in + (j + 0.5) * len / n;
-          const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
-          double rbar[4], zo;
-          orc_normalize(g, x, t, rbar);
-          sum += mlp_forward(m, B, P, rbar, &w, &zo);
-        }
-        const double pbar = (n > 0) ? m->mu0 * len / n * sum : 0.0;
+        const double pbar = (n_all > 0) ? m->mu0 * acc / (double)n_all : 0.0;
         if (proj) proj[r] = pbar;
         const double e = meas[r] - pbar;
         lpart[tid] += e * e;
-        if (n == 0) continue;
-        /* dL/dpbar_i = -2 (p_i - pbar_i) / R ; dpbar_i/dM_ij = mu0 l_i / n_i */
-        const double dM = (-2.0 * e / (double)R) * (m->mu0 * len / n);
-        for (int32_t j = 0; j < n; ++j) {
-          const double s = s_in + (j + 0.5) * len / n;
-          const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
-          double rbar[4], zo;
-          orc_normalize(g, x, t, rbar);
-          mlp_forward(m, B, P, rbar, &w, &zo);
-          mlp_backward(m, P, &w, zo, dM, gl);
+        if (n_all == 0) continue;
+        for (int32_t k = 0; k < D2; ++k) {
+          double o[3], d[3], t, s_in, len;
+          orc_subray(g, idx[r], D, k, o, d, &t);
+          orc_clip(g, o, d, &s_in, &len);
+          int32_t n = n_override ? n_override[r * D2 + k] : orc_nsamp(sp, len);
+          if (!(len > 0.0)) n = 0;
+          /* dL/dpbar_i = -2 (p_i - pbar_i) / R ; dpbar_i/dM_kj = mu0 l_k / |Phi_i| */
+          const double dM = (-2.0 * e / (double)R) * (m->mu0 * len / (double)n_all);
+          for (int32_t j = 0; j < n; ++j) {
+            const double s = s_in + (j + 0.5) * len / n;
+            const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
+            double rbar[4], zo;
+            orc_normalize(g, x, t, rbar);
+            mlp_forward(m, B, P, rbar, &w, &zo);
+            mlp_backward(m, P, &w, zo, dM, gl);
+          }
         }
       }
     }

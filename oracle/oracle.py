@@ -46,7 +46,8 @@ class _MLP(C.Structure):
 
 class _Samp(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n", C.c_int32), ("n_min", C.c_int32),
-                ("n_max", C.c_int32), ("h", C.c_double)]
+                ("n_max", C.c_int32), ("h", C.c_double), ("sub", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class _Field(C.Structure):
@@ -66,6 +67,8 @@ def lib():
         d, i32, i64 = C.c_double, C.c_int32, C.c_int64
         L.orc_ray.argtypes = [P(_Geom), i64, P(d), P(d), P(d)]
         L.orc_ray.restype = C.c_int
+        L.orc_subray.argtypes = [P(_Geom), i64, i32, i32, P(d), P(d), P(d)]
+        L.orc_subray.restype = C.c_int
         L.orc_clip.argtypes = [P(_Geom), P(d), P(d), P(d), P(d)]
         L.orc_clip.restype = None
         L.orc_nsamp.argtypes = [P(_Samp), d]
@@ -130,7 +133,14 @@ def _mlp(m) -> _MLP:
 def _samp(sp) -> _Samp:
     s = _Samp()
     s.mode, s.n, s.n_min, s.n_max, s.h = sp.mode, sp.n, sp.n_min, sp.n_max, sp.h
+    s.sub = getattr(sp, "sub", 1)
     return s
+
+
+def sub_rays(sp) -> int:
+    """Rays per projection, D^2."""
+    D = max(1, getattr(sp, "sub", 1))
+    return D * D
 
 
 def threads() -> int:
@@ -147,6 +157,17 @@ def ray(g, i: int):
     rc = lib().orc_ray(C.byref(_geom(g, keep)), int(i), _dp(o), _dp(d), _dp(t))
     if rc != 0:
         raise IndexError(i)
+    return o, d, float(t[0])
+
+
+def subray(g, i: int, D: int, k: int):
+    """Ray k = b D + a of projection i: to the centre of sub-pixel (b, a)."""
+    keep = _Keep()
+    o, d, t = np.zeros(3), np.zeros(3), np.zeros(1)
+    rc = lib().orc_subray(C.byref(_geom(g, keep)), int(i), int(D), int(k), _dp(o), _dp(d),
+                          _dp(t))
+    if rc != 0:
+        raise IndexError((i, D, k))
     return o, d, float(t[0])
 
 
@@ -173,15 +194,17 @@ def normalize(g, x, t):
 
 def forward(g, m, sp, B, params, idx, field: Optional[tuple] = None,
             n_override: Optional[np.ndarray] = None, nthreads: int = 0):
-    """pbar [R] (float64), n [R], s_in [R], l [R].  field = (kind, data[n,k])
-    replaces the MLP by an analytic field."""
+    """pbar [R] (float64), and n, s_in, l of every ray, [R D^2] (ray k of
+    projection r at r D^2 + k).  field = (kind, data[n,k]) replaces the MLP by
+    an analytic field; n_override is [R D^2]."""
     keep = _Keep()
     idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
     R = idx.shape[0]
+    RS = R * sub_rays(sp)
     Bd = keep.f64(B if B is not None else np.zeros((1, 4)))
     Pd = keep.f64(params if params is not None else np.zeros(1))
-    proj, si, ln = np.zeros(R), np.zeros(R), np.zeros(R)
-    n = np.zeros(R, dtype=np.int32)
+    proj, si, ln = np.zeros(R), np.zeros(RS), np.zeros(RS)
+    n = np.zeros(RS, dtype=np.int32)
     fs = None
     if field is not None:
         kind, data = field
@@ -193,6 +216,7 @@ def forward(g, m, sp, B, params, idx, field: Optional[tuple] = None,
     nov = None
     if n_override is not None:
         nov = np.ascontiguousarray(np.asarray(n_override, dtype=np.int32))
+        assert nov.shape == (RS,), "n_override holds one count per ray"
         keep.refs.append(nov)
     rc = lib().orc_forward(C.byref(_geom(g, keep)), C.byref(_mlp(m)), C.byref(_samp(sp)),
                            C.byref(fs) if fs is not None else None, _dp(Bd), _dp(Pd),
@@ -217,6 +241,7 @@ def step(g, m, sp, B, params, idx, meas, n_override=None, nthreads: int = 0):
     nov = None
     if n_override is not None:
         nov = np.ascontiguousarray(np.asarray(n_override, dtype=np.int32))
+        assert nov.shape == (R * sub_rays(sp),), "n_override holds one count per ray"
         keep.refs.append(nov)
     rc = lib().orc_step(C.byref(_geom(g, keep)), C.byref(_mlp(m)), C.byref(_samp(sp)), _dp(Bd),
                         _dp(Pd), idx.ctypes.data_as(C.POINTER(C.c_int64)), R, _dp(Md),

@@ -104,6 +104,7 @@ class Sampling:
     h: float = 1.0 / 256
     n_min: int = 32
     n_max: int = 512
+    sub: int = 1                     # D: D x D rays per projection (Appendix A)
 
 
 @dataclasses.dataclass

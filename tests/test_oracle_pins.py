@@ -461,3 +461,114 @@ def test_adam_first_step_closed_form():
     mm, vv = np.zeros(50), np.zeros(50)
     O.adam(p, gr, mm, vv, 1e-3, 0.9, 0.999, 1e-8, 1)
     np.testing.assert_allclose(p, p0 - 1e-3 * gr / (np.abs(gr) + 1e-8), rtol=0, atol=1e-15)
+
+
+# ------------------------------------- D x D rays per projection (Appendix A)
+
+def refined(g, D):
+    """The same scanner with a detector D times finer in each direction."""
+    return dataclass_replace(g, rows=g.rows * D, cols=g.cols * D, pitch_u=g.pitch_u / D,
+                             pitch_v=g.pitch_v / D)
+
+
+def refined_indices(g, D, i):
+    """Projection indices, on the refined detector, of the D x D sub-pixels of
+    projection i, in ray order k = b D + a."""
+    N = g.rows * g.cols
+    m, n = divmod(int(i), N)
+    row, col = divmod(n, g.cols)
+    return [m * N * D * D + (D * row + b) * (g.cols * D) + (D * col + a)
+            for b in range(D) for a in range(D)]
+
+
+@pytest.mark.parametrize("kind", ["parallel", "cone"])
+@pytest.mark.parametrize("D", [2, 3])
+def test_subrays_end_at_refined_detector_centres(kind, D):
+    """Ray k of a projection ends at the centre of sub-pixel k, which is the
+    centre of a pixel of a detector D times finer."""
+    g = geom_parallel() if kind == "parallel" else geom_cone()
+    gf = refined(g, D)
+    for i in [centre_index(g, 1), centre_index(g, 2) + 5 * g.cols - 7, 3]:
+        for k, j in enumerate(refined_indices(g, D, i)):
+            o, d, t = O.subray(g, i, D, k)
+            o2, d2, t2 = O.ray(gf, j)
+            np.testing.assert_allclose(o, o2, atol=1e-12)
+            np.testing.assert_allclose(d, d2, atol=1e-15)
+            assert t == t2
+    o, d, t = O.subray(g, 7, 1, 0)
+    o2, d2, t2 = O.ray(g, 7)
+    assert np.array_equal(o, o2) and np.array_equal(d, d2) and t == t2
+
+
+@pytest.mark.parametrize("kind", ["parallel", "cone"])
+def test_bundle_with_fixed_counts_is_the_mean_of_refined_rays(kind):
+    """Fixed n and every ray inside the FOV: |Phi_i| = D^2 n, so pbar_i is the
+    mean of the D^2 single-ray predictions of the refined detector."""
+    D = 2
+    g = geom_parallel() if kind == "parallel" else geom_cone()
+    m = S.MLPSpec(n_freq=4, width=8, depth=2, act=1, out_act=1, mu0=1.3, sigma_t=1.0,
+                  sigma_s=1.0)
+    B = S.make_B(m, 11).astype(np.float64)
+    P = S.make_params(m, 12).astype(np.float64)
+    N = g.rows * g.cols
+    c = centre_index(g)
+    idx = np.array([c, c + 2, c - 3 * g.cols, N + c + 4 * g.cols - 5, 3 * N + c + 7])
+    p2, n2, _, l2 = O.forward(g, m, S.Sampling(mode=0, n=12, sub=D), B, P, idx)
+    fine = np.array([refined_indices(g, D, i) for i in idx]).ravel()
+    p1, n1, _, l1 = O.forward(refined(g, D), m, S.Sampling(mode=0, n=12), B, P, fine)
+    assert np.all(n2 == 12) and np.array_equal(n1, n2)
+    np.testing.assert_allclose(l2, l1, rtol=1e-14)
+    np.testing.assert_allclose(p2, p1.reshape(-1, D * D).mean(axis=1), rtol=1e-12)
+
+
+def test_bundle_weights_with_variable_counts_closed_form():
+    """Sample count per ray from its own chord: with a constant field M = c,
+    pbar = mu0 c sum_k l_k n_k / sum_k n_k, with the closed-form chords
+    l_k = 2 sqrt(R^2 - u_k^2) of parallel rays through a cylinder at theta = 0
+    (u_k the sub-pixel centres) and n_k = ceil(l_k / h)."""
+    g = geom_parallel(rows=9, cols=9, n_views=1, fov_kind=1, fov=(0.8, -0.5, 0.5, 0, 0, 0),
+                      pitch=0.15)
+    D, h, mu0, cval = 3, 0.07, 1.1, 0.6
+    sp = S.Sampling(mode=1, h=h, n_min=1, n_max=1000, sub=D)
+    m = S.MLPSpec(mu0=mu0)
+    idx = np.array([4 * 9 + 6, 4 * 9 + 7, 2 * 9 + 7, 6 * 9 + 1])  # off-centre: chords vary
+    proj, n, _, ln = O.forward(g, m, sp, None, None, idx, field=(1, (cval, 0, 0, 0, 0)))
+    for r, i in enumerate(idx):
+        row, col = divmod(int(i), g.cols)
+        num = den = 0.0
+        for b in range(D):
+            for a in range(D):
+                u = (col + (a + 0.5) / D - 0.5 - (g.cols - 1) / 2) * g.pitch_u
+                v = (row + (b + 0.5) / D - 0.5 - (g.rows - 1) / 2) * g.pitch_v
+                lk = 2 * math.sqrt(0.8 ** 2 - u ** 2) if abs(u) < 0.8 and abs(v) <= 0.5 else 0.0
+                nk = math.ceil(lk / h) if lk > 0 else 0
+                assert n[r * D * D + b * D + a] == nk
+                num += lk * nk
+                den += nk
+        assert len(set(n[r * D * D:(r + 1) * D * D])) > 1  # the counts do differ
+        assert abs(proj[r] - mu0 * cval * num / den) < 1e-13
+
+
+def test_bundle_gradient_central_differences():
+    """The adjoint of the D x D estimator (variable counts, cone beam, Swish):
+    central differences of the oracle's own forward on every parameter."""
+    th = np.arange(3) * 2 * math.pi / 3
+    g = S.Geometry(kind=1, rows=7, cols=7, n_views=3, sod=3.0, sdd=6.0, pitch_u=0.5,
+                   pitch_v=0.5, theta=th, time=np.arange(3) / 3)
+    m = S.MLPSpec(n_freq=3, width=6, depth=2, act=1, out_act=1, mu0=0.9, sigma_t=1.0,
+                  sigma_s=1.5)
+    B = S.make_B(m, 21).astype(np.float64)
+    P = S.make_params(m, 22).astype(np.float64)
+    sp = S.Sampling(mode=1, h=0.45, n_min=2, n_max=9, sub=2)
+    idx = S.draw_rays(g, 5, 23)
+    meas = np.random.default_rng(2).uniform(0, 2, 5)
+    _, n, _, _ = O.forward(g, m, sp, B, P, idx)
+    assert len(set(n.tolist())) > 1
+    loss, grad, _ = O.step(g, m, sp, B, P, idx, meas)
+    assert abs(loss - loss_of(g, m, sp, B, P, idx, meas)) < 1e-14
+    for k in range(P.size):
+        hk = 1e-6 * max(1.0, abs(P[k]))
+        Pp = P.copy(); Pp[k] += hk
+        Pm = P.copy(); Pm[k] -= hk
+        fd = (loss_of(g, m, sp, B, Pp, idx, meas) - loss_of(g, m, sp, B, Pm, idx, meas)) / (2 * hk)
+        assert abs(fd - grad[k]) <= 1e-7 * np.abs(grad).max() + 1e-10, k
