@@ -101,15 +101,22 @@ typedef struct {
   double mu0;
 } dinr_mlp;
 
-/* Samples per ray (Appendix A): equi-spaced midpoints of n equal segments of
- * the ray's chord inside the FOV.  mode 0: n fixed; mode 1: n = clamp(ceil(l/h),
- * n_min, n_max) with l the chord length.  A ray missing the FOV has n = 0 and
- * predicted projection 0. */
+/* Rays and samples of a projection (Appendix A).  Each projection's pixel is
+ * divided into D x D sub-pixels and one ray is traced to the centre of each
+ * (sub = D; 0 is read as 1, at most 8).  Samples are equi-spaced midpoints of
+ * n equal segments of each ray's chord inside the FOV: mode 0: n fixed;
+ * mode 1: n = clamp(ceil(l/h), n_min, n_max) with l the chord length.  The
+ * prediction averages mu0 l M over the samples of all D^2 rays, each weighted
+ * by its own ray's chord.  A ray missing the FOV has n = 0; a projection none
+ * of whose rays hits it is predicted 0.  D > 1 takes the two-pass training
+ * step; the query server always traces one ray per pixel. */
 typedef struct {
   int32_t mode;
   int32_t n;
   int32_t n_min, n_max;
   double h;
+  int32_t sub;       /* D */
+  int32_t reserved;
 } dinr_sampling;
 
 /* Adam state for dinr_step (Sec. II, Appendix C).  m_d, v_d: device FP32
@@ -141,12 +148,15 @@ const char* dinr_last_error(const dinr_ctx* ctx);
 /* Number of parameters of the context's network. */
 int64_t dinr_num_params(const dinr_ctx* ctx);
 
-/* Forward projection, Eq. (1)/(7): for each ray r of the batch,
- * proj_out_d[r] = (1/n_r) sum_j mu0 l_r M(r_{r,j}; gamma).
+/* Forward projection, Eq. (1)/(7) and Appendix A: for each projection r of
+ * the batch, proj_out_d[r] = (1/|Phi_r|) sum_j mu0 l_j M(r_j; gamma) over the
+ * samples j of its D^2 rays (l_j: the chord of the ray holding sample j; for
+ * D = 1, (1/n_r) sum_j mu0 l_r M(r_{r,j})).
  * params_d: device FP32 [n_params].  proj_idx_d: device int64 [R], each in
  * [0, n_views*rows*cols) (checked on the device: an out-of-range index yields
  * n = 0 and projection NaN).  proj_out_d: device FP32 [R].  n_out_d: device
- * int32 [R] receiving the sample count of each ray, or NULL. */
+ * int32 [R] receiving |Phi_r|, the sample count of each projection, or NULL.
+ * R D^2 must stay below 2^31 - 1. */
 int dinr_forward_project(dinr_ctx* ctx, const float* params_d, const int64_t* proj_idx_d,
                          int64_t R, float* proj_out_d, int32_t* n_out_d, void* stream);
 

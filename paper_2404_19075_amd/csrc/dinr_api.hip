@@ -34,7 +34,8 @@ struct Arena {
 
 // Everything one call needs, carved from the arena.
 struct Plan {
-  int64_t R = 0, n_tiles_max = 0, points_max = 0;
+  // R: ray records (Rp projections x D^2 rays each)
+  int64_t R = 0, Rp = 0, D2 = 1, n_tiles_max = 0, points_max = 0;
   RayRec* rays = nullptr;
   int32_t* nray = nullptr;
   int64_t* off = nullptr;
@@ -42,6 +43,8 @@ struct Plan {
   float* part = nullptr;
   float* gup = nullptr;
   float* proj = nullptr;
+  float* ray_proj = nullptr;  // D > 1: weighted sums of the single rays
+  float* gproj = nullptr;     // D > 1: upstream gradient of the projections
   void* Wpk = nullptr;
   void* WTpk = nullptr;
   float* bias = nullptr;
@@ -67,7 +70,12 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
   // status and scalars live at the start of the arena
   c->d_status = A.take<int32_t>(4);
   c->d_scal = A.take<double>(4);
-  p->R = R;
+  p->Rp = R;
+  p->D2 = (int64_t)c->gd.sub * c->gd.sub;
+  p->R = R * p->D2;
+  R = p->R;
+  if (R > (int64_t)INT32_MAX - 1)
+    return fail(c, DINR_EINVAL, "R D^2 = %lld rays exceeds 2^31 - 2", (long long)R);
   p->points_max = R * (int64_t)c->nmax;
   p->n_tiles_max = (p->points_max + c->tile - 1) / c->tile;
   p->rays = A.take<RayRec>(std::max<int64_t>(R, 1));
@@ -76,7 +84,11 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
   p->tr0 = A.take<int32_t>(p->n_tiles_max + 1);
   p->part = A.take<float>(2 * std::max<int64_t>(p->n_tiles_max, 1));
   p->gup = A.take<float>(std::max<int64_t>(R, 1));
-  p->proj = A.take<float>(std::max<int64_t>(R, 1));
+  p->proj = A.take<float>(std::max<int64_t>(p->Rp, 1));
+  if (p->D2 > 1) {
+    p->ray_proj = A.take<float>(R);
+    p->gproj = A.take<float>(p->Rp);
+  }
   // packed weights
   p->pk = pack_layout(c);
   const PackArgs& k = p->pk;
@@ -172,18 +184,22 @@ static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
 
 static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
                            const int64_t* idx, float* proj, int32_t* n_out, hipStream_t st) {
-  HIPCHK(c, launch_rays(c->gd, idx, p.R, p.rays, p.nray, n_out, p.off, c->tile, p.n_tiles_max,
+  HIPCHK(c, launch_rays(c->gd, idx, p.Rp, p.rays, p.nray, n_out, p.off, c->tile, p.n_tiles_max,
                         p.tr0, st));
   HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
                         p.bias, p.wo, st));
   MlpArgs a = mlp_args(c, p, params);
-  a.proj = proj;
+  // the kernel writes one sum per ray record: with D > 1 those are the single
+  // rays, summed into the projections below
+  float* ray_out = p.D2 > 1 ? p.ray_proj : proj;
+  a.proj = ray_out;
   {
     ProfScope ps(c, DINR_PROF_MLP_FWD, st);
     HIPCHK(c, launch_mlp(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, c->IN, c->H, MODE_FWD, a,
                          p.grid_mlp, st));
   }
-  HIPCHK(c, launch_fixup(p.rays, p.off, p.R, c->tile, p.part, proj, st));
+  HIPCHK(c, launch_fixup(p.rays, p.off, p.R, c->tile, p.part, ray_out, st));
+  if (p.D2 > 1) HIPCHK(c, launch_bundle(p.ray_proj, p.Rp, (int)p.D2, proj, st));
   return DINR_OK;
 }
 
@@ -314,6 +330,7 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
       rc = bad("sampling mode");
       break;
     }
+    if (s->sub < 0 || s->sub > 8) { rc = bad("rays per projection: D must be in [1, 8]"); break; }
     for (int k = 0; k < 4 * m->n_freq; ++k)
       if (!std::isfinite(B_host[k])) { rc = bad("B has a non-finite entry"); break; }
     if (rc) break;
@@ -400,6 +417,7 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
   d.samp_min = s->n_min;
   d.samp_max = s->n_max;
   d.samp_h = (float)s->h;
+  d.sub = s->sub > 1 ? s->sub : 1;
   d.sod = (float)g->sod;
   d.sdd = (float)g->sdd;
   d.pitch_u = (float)g->pitch_u;
@@ -505,6 +523,10 @@ int dinr_project_backward(dinr_ctx* c, const float* params, const int64_t* idx, 
                         p.tr0, st));
   HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
                         p.bias, p.wo, st));
+  if (p.D2 > 1) {
+    HIPCHK(c, launch_expand(dproj, R, (int)p.D2, p.gup, st));
+    dproj = p.gup;
+  }
   return enqueue_adjoint(c, p, params, dproj, grad, gnorm, st);
 }
 
@@ -528,8 +550,9 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   HIPCHK(c, hipSetDevice(c->device));
   float* proj = proj_out ? proj_out : p.proj;
   // the one-pass kernel exists for ReLU networks only
+  // (and for one ray per projection: its tiles must hold whole projections)
   const bool fused = !c->mlp.recompute && c->mlp.act == DINR_RELU && c->samp.mode == 0 &&
-                     c->tile % c->samp.n == 0;
+                     c->tile % c->samp.n == 0 && p.D2 == 1;
   if (fused) {
     HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
                           p.tr0, st));
@@ -542,7 +565,8 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   } else {
     rc = enqueue_forward(c, p, params, idx, proj, nullptr, st);
     if (rc) return rc;
-    HIPCHK(c, launch_loss(proj, meas, R, p.gup, c->d_scal, st));
+    HIPCHK(c, launch_loss(proj, meas, R, p.D2 > 1 ? p.gproj : p.gup, c->d_scal, st));
+    if (p.D2 > 1) HIPCHK(c, launch_expand(p.gproj, R, (int)p.D2, p.gup, st));
     if (loss)
       HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
     rc = enqueue_adjoint(c, p, params, p.gup, grad, gnorm, st);

@@ -37,6 +37,7 @@ struct GeomDev {
   int kind, rows, cols, n_views, fov_kind;
   int samp_mode, samp_n, samp_min, samp_max;
   float samp_h;
+  int sub;  // D: D x D rays per projection
   float sod, sdd, pitch_u, pitch_v, off_u, off_v;
   float fov[6];
   float sc[3], oc[3];  // x_norm = x * sc + oc per axis (x, y, z)
@@ -125,6 +126,9 @@ struct RedArgs {
   double* gn_part;
 };
 
+// R projections -> R D^2 ray records; n_out (nullable) is per projection
+hipError_t launch_bundle(const float* ray_proj, int64_t R, int D2, float* proj, hipStream_t st);
+hipError_t launch_expand(const float* g_proj, int64_t R, int D2, float* g_ray, hipStream_t st);
 hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* rays, int32_t* nray,
                        int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
                        hipStream_t st);

@@ -1,6 +1,9 @@
 // kernels.hip -- gfx950 kernels of one DINR training step.
 //
-//   k_rays       per ray: index -> view/pixel -> ray, FOV clip, sample count
+//   k_rays       per projection: index -> view/pixel -> its D x D rays, FOV clip,
+//                sample counts
+//   k_bundle     projection = sum of its rays' weighted sums (D > 1)
+//   k_expand     upstream gradient of each ray = that of its projection (D > 1)
 //   k_scan       exclusive scan of sample counts -> ragged point offsets
 //   k_tiles      first ray of every point tile
 //   k_pack       FP32 parameters -> matrix-core operand fragments (W and W^T)
@@ -28,9 +31,11 @@ namespace dinr {
 // (Appendix B item 1).
 // Ray through detector position (u, v) of a view rotated by theta (c = cos,
 // s = sin), clipped to the FOV, with its sample count (fixed n, or
-// clamp(ceil(l/h)) when samp_mode = 1).
+// clamp(ceil(l/h)) when samp_mode = 1).  Its weight is mu0 l / |Phi|, with
+// |Phi| = n_phi, the samples of all rays of the projection (Appendix A), or
+// the ray's own n when n_phi is 0.
 __device__ inline RayRec make_ray(const GeomDev& g, float u, float v, float c, float s, float tn,
-                                  int samp_mode, int samp_n) {
+                                  int samp_mode, int samp_n, int n_phi = 0) {
   float p0x, p0y, p0z, d0x, d0y, d0z;
   if (g.kind == 0) {
     p0x = 0.f; p0y = u; p0z = v;
@@ -106,17 +111,21 @@ __device__ inline RayRec make_ray(const GeomDev& g, float u, float v, float c, f
   rec.s_in = (n > 0) ? lo : 0.f;
   rec.dl = (n > 0) ? len / (float)n : 0.f;
   rec.tn = tn;
-  rec.wgt = (n > 0) ? g.mu0 * len / (float)n : 0.f;
+  rec.wgt = (n > 0) ? g.mu0 * len / (float)(n_phi > 0 ? n_phi : n) : 0.f;
   rec.n = n;
   rec.flags = 0;
   return rec;
 }
 
+// One thread per projection: its D x D rays (Appendix A), ray k = b D + a to
+// the centre of sub-pixel (b, a), at records r D^2 + k.  n_out[r] = |Phi_r|,
+// the samples of all of them.
 __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
                        RayRec* __restrict__ rays, int32_t* __restrict__ nray,
                        int32_t* __restrict__ n_out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
+  const int D = g.sub, D2 = D * D;
   const int64_t i = idx[r];
   const int64_t N = (int64_t)g.rows * g.cols;
   if (i < 0 || i >= N * g.n_views) {
@@ -127,8 +136,10 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     rec.wgt = 0.f;
     rec.n = 0;
     rec.flags = 1;
-    rays[r] = rec;
-    nray[r] = 0;
+    for (int k = 0; k < D2; ++k) {
+      rays[r * D2 + k] = rec;
+      nray[r * D2 + k] = 0;
+    }
     if (n_out) n_out[r] = 0;
     return;
   }
@@ -138,10 +149,46 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
   const int col = (int)(pix - (int64_t)row * g.cols);
   const float u = ((float)col - 0.5f * (float)(g.cols - 1)) * g.pitch_u + g.off_u;
   const float v = ((float)row - 0.5f * (float)(g.rows - 1)) * g.pitch_v + g.off_v;
-  const RayRec rec = make_ray(g, u, v, g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode, g.samp_n);
-  rays[r] = rec;
-  nray[r] = rec.n;
-  if (n_out) n_out[r] = rec.n;
+  if (D == 1) {
+    const RayRec rec = make_ray(g, u, v, g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode, g.samp_n);
+    rays[r] = rec;
+    nray[r] = rec.n;
+    if (n_out) n_out[r] = rec.n;
+    return;
+  }
+  // sub-pixel centre offsets (k % D + 1/2) / D - 1/2 in pixels
+  auto sub_u = [&](int k) { return u + (float)(2 * (k % D) + 1 - D) / (float)(2 * D) * g.pitch_u; };
+  auto sub_v = [&](int k) { return v + (float)(2 * (k / D) + 1 - D) / (float)(2 * D) * g.pitch_v; };
+  int n_phi = 0;
+  for (int k = 0; k < D2; ++k)
+    n_phi += make_ray(g, sub_u(k), sub_v(k), g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode,
+                      g.samp_n).n;
+  for (int k = 0; k < D2; ++k) {
+    const RayRec rec = make_ray(g, sub_u(k), sub_v(k), g.cth[m], g.sth[m], g.tnorm[m],
+                                g.samp_mode, g.samp_n, n_phi);
+    rays[r * D2 + k] = rec;
+    nray[r * D2 + k] = rec.n;
+  }
+  if (n_out) n_out[r] = n_phi;
+}
+
+// pbar of each projection: the sum of its D^2 rays' weighted sums (the
+// weights already carry 1/|Phi|), added in FP64 and rounded once.
+__global__ void k_bundle(const float* __restrict__ ray_proj, int64_t R, int D2,
+                         float* __restrict__ proj) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double acc = 0.0;
+  for (int k = 0; k < D2; ++k) acc += (double)ray_proj[r * D2 + k];
+  proj[r] = (float)acc;
+}
+
+// dL/d(ray sum) of each ray = dL/dpbar of its projection.
+__global__ void k_expand(const float* __restrict__ g_proj, int64_t R, int D2,
+                         float* __restrict__ g_ray) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= R * D2) return;
+  g_ray[q] = g_proj[q / D2];
 }
 
 // Exclusive scan of n[R] into off[R+1] (one workgroup; R is at most a few
@@ -1514,12 +1561,29 @@ hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* 
                        int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
                        hipStream_t st) {
   const int bs = 256;
+  const int64_t n_rec = R * g.sub * g.sub;  // ray records
   if (R > 0)
     hipLaunchKernelGGL(k_rays, dim3((unsigned)((R + bs - 1) / bs)), dim3(bs), 0, st, g, idx, R, rays,
                        nray, n_out);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nray, R, off);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nray, n_rec, off);
   hipLaunchKernelGGL(k_tiles, dim3((unsigned)((n_tiles_max + 1 + bs - 1) / bs)), dim3(bs), 0, st,
-                     off, R, tile, n_tiles_max, tr0);
+                     off, n_rec, tile, n_tiles_max, tr0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bundle(const float* ray_proj, int64_t R, int D2, float* proj, hipStream_t st) {
+  const int bs = 256;
+  if (R > 0)
+    hipLaunchKernelGGL(k_bundle, dim3((unsigned)((R + bs - 1) / bs)), dim3(bs), 0, st, ray_proj, R,
+                       D2, proj);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const float* g_proj, int64_t R, int D2, float* g_ray, hipStream_t st) {
+  const int bs = 256;
+  if (R > 0)
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)((R * D2 + bs - 1) / bs)), dim3(bs), 0, st, g_proj,
+                       R, D2, g_ray);
   return hipGetLastError();
 }
 

@@ -45,7 +45,8 @@ class MLP(C.Structure):
 
 class Sampling(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n", C.c_int32), ("n_min", C.c_int32),
-                ("n_max", C.c_int32), ("h", C.c_double)]
+                ("n_max", C.c_int32), ("h", C.c_double), ("sub", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -162,6 +163,7 @@ class Context:
         s = Sampling()
         s.mode, s.n, s.n_min, s.n_max, s.h = (sampling.mode, sampling.n, sampling.n_min,
                                               sampling.n_max, sampling.h)
+        s.sub = getattr(sampling, "sub", 1)
         Bh = np.ascontiguousarray(np.asarray(B, dtype=np.float32))
         h = C.c_void_p()
         rc = L.dinr_create(C.byref(g), C.byref(m), C.byref(s),

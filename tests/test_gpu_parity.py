@@ -380,3 +380,57 @@ def test_swish_recompute_flag_is_the_same_step():
     o2 = run_step(w, b, BF16, recompute=True)
     assert np.array_equal(o1["proj"], o2["proj"])
     assert np.array_equal(o1["grad"], o2["grad"])
+
+
+def with_sub(w, D, **samp):
+    return dataclasses.replace(w, sampling=dataclasses.replace(w.sampling, sub=D, **samp))
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_subpixel_rays_c0(prec):
+    """D x D rays per projection (Appendix A, D = 2) on c0: every projection
+    averages the samples of its 4 rays; the step takes the two-pass route."""
+    w = with_sub(S.workload("c0"), 2)
+    b = S.make_batch(w)
+    log(f"test_subpixel_rays_c0 prec={prec}")
+    proj_g, n_g = run_forward(w, b, prec)
+    ref, n_ref, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx)
+    assert np.array_equal(n_g, n_ref.reshape(-1, 4).sum(axis=1))
+    ep = rel(proj_g, ref)
+    log(f"  forward proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[prec]
+    out = run_step(w, b, prec)
+    loss, grad, proj = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas)
+    ep2, el = rel(out["proj"], proj), abs(out["loss"] - loss) / loss
+    log(f"  step proj {ep2:.3e} loss {el:.3e}")
+    assert ep2 <= TOL_PROJ[prec]
+    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c0 D=2 prec={prec}")
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_subpixel_rays_cone_variable_counts(prec):
+    """Cone beam with n = clamp(ceil(l/h)) per ray and D = 2 (c3 geometry and
+    network, 48 projections): |Phi| sums counts that differ between the rays
+    of one projection, each sample weighted by its own ray's chord."""
+    w = with_sub(small_workload("c3", 48), 2)
+    b = S.make_batch(w)
+    log(f"test_subpixel_rays_cone_variable_counts prec={prec}")
+    proj_g, n_g = run_forward(w, b, prec)
+    _, n_ref, _, ln = O.forward(w.geom, w.mlp, w.sampling, None, None, b.idx,
+                                field=(1, (0, 0, 0, 0, 0)))
+    q = ln / w.sampling.h
+    tie = (np.abs(q - np.round(q)) < 1e-4 * np.maximum(q, 1)).reshape(-1, 4).any(axis=1)
+    same = n_g == n_ref.reshape(-1, 4).sum(axis=1)
+    log(f"  projections {len(n_g)}, count mismatches {int((~same).sum())}, near ties {int(tie.sum())}")
+    assert np.all(same | tie)
+    assert np.any(n_ref.reshape(-1, 4).min(axis=1) != n_ref.reshape(-1, 4).max(axis=1))
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx)
+    ep = rel(proj_g[same], ref[same])
+    log(f"  proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[prec]
+    if np.all(same):
+        out = run_step(w, b, prec)
+        loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas)
+        log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e}")
+        check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 D=2 prec={prec}")
