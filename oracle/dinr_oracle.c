@@ -21,6 +21,8 @@
  *     w = mu0 * l (chord length in the FOV): Appendix A, Eqs. (1), (2), (7)
  *   - D x D rays per projection, one to the centre of each sub-pixel, and
  *     pbar the average over the samples of all of them: Appendix A
+ *   - randomly placed samples along the rays (Sec. IV): optionally, sample j
+ *     sits at a uniformly random position inside segment j
  *   - coordinate normalisation to [-1,1], Gaussian random Fourier features
  *     [cos 2 pi B r ; sin 2 pi B r], FC layers, scalar output: Appendix B
  *   - squared distance, local loss, gradient: Eqs. (3), (5), (8)
@@ -36,6 +38,11 @@
  *   - a ray that misses the FOV has n = 0 and prediction 0.
  *   - with D > 1, |Phi_i| counts the samples of all D^2 rays and each sample
  *     is weighted by the chord length of its own ray.
+ *   - random placement is stratified (one sample per segment, so the weights
+ *     stay mu0 l / |Phi|); the uniform offset u of sample j of ray k of
+ *     projection i comes from Philox4x32-10 (Salmon et al., SC'11) with key
+ *     (seed, epoch) and counter (j, k, i mod 2^32, i div 2^32): u = (x0 >> 8) 2^-24
+ *     of the first output word, so both implementations draw the same u.
  *
  * Parameter layout (flat, FP64 here): for l = 1..L: W_l [H x fan_in]
  * row-major (row = output unit), b_l [H]; then w_o [H], b_o [1].
@@ -81,7 +88,9 @@ typedef struct {
   int32_t n_min, n_max;
   double h;
   int32_t sub;      /* D: rays per projection D x D (0 is read as 1; at most 16) */
-  int32_t pad_;
+  int32_t jitter;   /* 1: stratified random positions instead of midpoints */
+  uint32_t seed;    /* first key word of the position generator */
+  uint32_t epoch;   /* second key word: one value per training step */
 } orc_sampling;
 
 /* Analytic replacement fields used to pin the geometry and the quadrature.
@@ -147,6 +156,40 @@ int orc_ray(const orc_geom* g, int64_t i, double o[3], double d[3], double* t) {
 }
 
 static int32_t sub_of(const orc_sampling* s) { return s->sub > 1 ? s->sub : 1; }
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplications with the
+ * round constants 0xD2511F53 and 0xCD9E8D57, the key bumped by the Weyl
+ * constants 0x9E3779B9 and 0xBB67AE85 between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * x0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Position of sample j inside its segment, in [0, 1): 1/2 (the midpoint), or
+ * the stratified random offset of sample j of ray k of projection i. */
+double orc_offset(const orc_sampling* s, int64_t i, int32_t k, int32_t j) {
+  if (!s->jitter) return 0.5;
+  const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)k, (uint32_t)((uint64_t)i & 0xFFFFFFFFu),
+                           (uint32_t)((uint64_t)i >> 32)};
+  const uint32_t key[2] = {s->seed, s->epoch};
+  uint32_t x[4];
+  orc_philox4x32_10(ctr, key, x);
+  return (double)(x[0] >> 8) * (1.0 / 16777216.0);
+}
 
 /* Chord of the ray inside the field of view: entry parameter and length.
  * Box: slab intersection.  Cylinder about z: quadratic in x,y plus a z slab.
@@ -420,7 +463,7 @@ static int ray_predict(const orc_geom* g, const orc_mlp* m, const orc_sampling* 
     if (!(len > 0.0)) n = 0;
     double sum = 0.0;
     for (int32_t j = 0; j < n; ++j) {
-      const double s = s_in + (j + 0.5) * len / n;
+      const double s = s_in + (j + orc_offset(sp, idx, k, j)) * len / n;
       const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
       double rbar[4], zo;
       orc_normalize(g, x, t, rbar);
@@ -523,7 +566,7 @@ int orc_step(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp, const 
           if (!(len > 0.0)) n = 0;
           double sum = 0.0;
           for (int32_t j = 0; j < n; ++j) {
-            const double s = s_in + (j + 0.5) * len / n;
+            const double s = s_in + (j + orc_offset(sp, idx[r], k, j)) * len / n;
             const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
             double rbar[4], zo;
             orc_normalize(g, x, t, rbar);
@@ -551,7 +594,7 @@ int orc_step(const orc_geom* g, const orc_mlp* m, const orc_sampling* sp, const 
           /* dL/dpbar_i = -2 (p_i - pbar_i) / R ; dpbar_i/dM_kj = mu0 l_k / |Phi_i| */
           const double dM = (-2.0 * e / (double)R) * (m->mu0 * len / (double)n_all);
           for (int32_t j = 0; j < n; ++j) {
-            const double s = s_in + (j + 0.5) * len / n;
+            const double s = s_in + (j + orc_offset(sp, idx[r], k, j)) * len / n;
             const double x[3] = {o[0] + s * d[0], o[1] + s * d[1], o[2] + s * d[2]};
             double rbar[4], zo;
             orc_normalize(g, x, t, rbar);

@@ -47,7 +47,7 @@ class _MLP(C.Structure):
 class _Samp(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n", C.c_int32), ("n_min", C.c_int32),
                 ("n_max", C.c_int32), ("h", C.c_double), ("sub", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("jitter", C.c_int32), ("seed", C.c_uint32), ("epoch", C.c_uint32)]
 
 
 class _Field(C.Structure):
@@ -69,6 +69,10 @@ def lib():
         L.orc_ray.restype = C.c_int
         L.orc_subray.argtypes = [P(_Geom), i64, i32, i32, P(d), P(d), P(d)]
         L.orc_subray.restype = C.c_int
+        L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_philox4x32_10.restype = None
+        L.orc_offset.argtypes = [P(_Samp), i64, i32, i32]
+        L.orc_offset.restype = d
         L.orc_clip.argtypes = [P(_Geom), P(d), P(d), P(d), P(d)]
         L.orc_clip.restype = None
         L.orc_nsamp.argtypes = [P(_Samp), d]
@@ -134,6 +138,9 @@ def _samp(sp) -> _Samp:
     s = _Samp()
     s.mode, s.n, s.n_min, s.n_max, s.h = sp.mode, sp.n, sp.n_min, sp.n_max, sp.h
     s.sub = getattr(sp, "sub", 1)
+    s.jitter = getattr(sp, "jitter", 0)
+    s.seed = getattr(sp, "seed", 0)
+    s.epoch = getattr(sp, "epoch", 0)
     return s
 
 
@@ -158,6 +165,20 @@ def ray(g, i: int):
     if rc != 0:
         raise IndexError(i)
     return o, d, float(t[0])
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter under a 2-word key (4 uint32 words)."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    out = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, out)
+    return [int(v) for v in out]
+
+
+def offset(sp, i: int, k: int, j: int) -> float:
+    """Position in [0, 1) of sample j of ray k of projection i in its segment."""
+    return float(lib().orc_offset(C.byref(_samp(sp)), int(i), int(k), int(j)))
 
 
 def subray(g, i: int, D: int, k: int):

@@ -105,6 +105,9 @@ class Sampling:
     n_min: int = 32
     n_max: int = 512
     sub: int = 1                     # D: D x D rays per projection (Appendix A)
+    jitter: int = 0                  # 1: stratified random sample positions (Sec. IV)
+    seed: int = 0                    # key words of the position generator
+    epoch: int = 0
 
 
 @dataclasses.dataclass

@@ -572,3 +572,77 @@ def test_bundle_gradient_central_differences():
         Pm = P.copy(); Pm[k] -= hk
         fd = (loss_of(g, m, sp, B, Pp, idx, meas) - loss_of(g, m, sp, B, Pm, idx, meas)) / (2 * hk)
         assert abs(fd - grad[k]) <= 1e-7 * np.abs(grad).max() + 1e-10, k
+
+
+# ------------------------------- randomly placed samples (Sec. IV), stratified
+
+def test_philox_known_answers():
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert O.philox4x32_10(v[0:4], v[4:6]) == v[6:10]
+
+
+def test_offsets_midpoint_without_jitter_and_uniform_with_it():
+    from scipy import stats
+    sp0 = S.Sampling(mode=0, n=8)
+    assert O.offset(sp0, 12345, 0, 3) == 0.5
+    sp = S.Sampling(mode=0, n=8, jitter=1, seed=77, epoch=5)
+    u = np.array([O.offset(sp, i, k, j) for i in (0, 1, 2**33 + 5) for k in range(4)
+                  for j in range(1500)])
+    assert np.all((u >= 0) & (u < 1))
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    # every key and counter word changes the draw
+    base = O.offset(sp, 9, 1, 2)
+    assert base != O.offset(sp, 9, 1, 3) and base != O.offset(sp, 9, 2, 2)
+    assert base != O.offset(sp, 9 + 2**32, 1, 2) and base != O.offset(sp, 10, 1, 2)
+    assert base != O.offset(dataclass_replace(sp, epoch=6), 9, 1, 2)
+    assert base != O.offset(dataclass_replace(sp, seed=78), 9, 1, 2)
+    # u = (x0 >> 8) 2^-24 of Philox(counter (j, k, i_lo, i_hi), key (seed, epoch))
+    x = O.philox4x32_10([2, 1, 9, 0], [77, 5])
+    assert base == (x[0] >> 8) / 2.0**24
+
+
+def test_stratified_jitter_is_unbiased():
+    """E[(l/n) sum_j f(s_in + (j + u_j) l/n)] = integral of f for independent
+    uniform u_j: the average over epochs converges to the exact line integral
+    of a moving Gaussian blob, within its standard error."""
+    g = geom_parallel(rows=17, cols=17, n_views=3)
+    c0, vel = np.array([0.1, -0.2, 0.05]), np.array([0.1, 0.05, -0.1])
+    sig, a = 0.35, 0.9
+    m = S.MLPSpec(mu0=1.0)
+    idx = S.draw_rays(g, 20, seed=3)
+    o, d, t = S.scanner_rays(g, idx)
+    s_in, ln = S.scanner_fov_chord(g, o, d)
+    exact = gaussian_line_integral(o, d, s_in, ln, c0[None, :] + vel[None, :] * t[:, None], sig, a)
+    blob = np.concatenate([c0, vel, [sig, a]])[None, :]
+    # one sample per ray: the midpoint rule is far off, the jittered mean not
+    K = 2000
+    runs = np.array([O.forward(g, m, S.Sampling(mode=0, n=1, jitter=1, seed=11, epoch=e), None,
+                               None, idx, field=(3, blob))[0] for e in range(K)])
+    mean, se = runs.mean(axis=0), runs.std(axis=0, ddof=1) / math.sqrt(K)
+    hit = ln > 0
+    assert np.all(se[hit] > 0)
+    assert np.all(np.abs(mean - exact)[hit] <= 5 * se[hit] + 1e-12)
+    mid = O.forward(g, m, S.Sampling(mode=0, n=1), None, None, idx, field=(3, blob))[0]
+    assert np.any(np.abs(mid - exact)[hit] > 10 * se[hit])  # the test can tell bias apart
+    again = O.forward(g, m, S.Sampling(mode=0, n=1, jitter=1, seed=11, epoch=7), None, None, idx,
+                      field=(3, blob))[0]
+    assert np.array_equal(again, runs[7])
+
+
+def test_jittered_gradient_central_differences():
+    """The adjoint evaluates the network at the same random positions as the
+    forward (D = 2, variable counts): central differences on every parameter."""
+    g, m, _, B, P, idx, meas = tiny_case(act=1, out_act=1, R=5)
+    sp = S.Sampling(mode=1, h=0.4, n_min=2, n_max=7, sub=2, jitter=1, seed=3, epoch=9)
+    loss, grad, _ = O.step(g, m, sp, B, P, idx, meas)
+    assert abs(loss - loss_of(g, m, sp, B, P, idx, meas)) < 1e-14
+    for k in range(P.size):
+        hk = 1e-6 * max(1.0, abs(P[k]))
+        Pp = P.copy(); Pp[k] += hk
+        Pm = P.copy(); Pm[k] -= hk
+        fd = (loss_of(g, m, sp, B, Pp, idx, meas) - loss_of(g, m, sp, B, Pm, idx, meas)) / (2 * hk)
+        assert abs(fd - grad[k]) <= 1e-7 * np.abs(grad).max() + 1e-10, k
