@@ -109,14 +109,23 @@ typedef struct {
  * prediction averages mu0 l M over the samples of all D^2 rays, each weighted
  * by its own ray's chord.  A ray missing the FOV has n = 0; a projection none
  * of whose rays hits it is predicted 0.  D > 1 takes the two-pass training
- * step; the query server always traces one ray per pixel. */
+ * step; the query server always traces one ray per pixel.
+ * jitter = 1 places the samples at random (Sec. IV), stratified: sample j of a
+ * ray sits at s_in + (j + u) l / n with u uniform in [0, 1), one draw per
+ * sample, so the weights are unchanged.  u = (x0 >> 8) 2^-24 with x0 the first
+ * word of Philox4x32-10 (Salmon et al., SC'11) of counter (j, k, i mod 2^32,
+ * i div 2^32) (k: the ray within projection i) under key (seed, epoch); the
+ * epoch is set per call with dinr_set_sample_epoch, so that every training
+ * step can draw new positions and any step can be replayed. */
 typedef struct {
   int32_t mode;
   int32_t n;
   int32_t n_min, n_max;
   double h;
   int32_t sub;       /* D */
-  int32_t reserved;
+  int32_t jitter;    /* 0 midpoints, 1 stratified random positions */
+  uint32_t seed;
+  uint32_t reserved;
 } dinr_sampling;
 
 /* Adam state for dinr_step (Sec. II, Appendix C).  m_d, v_d: device FP32
@@ -141,6 +150,11 @@ int dinr_create(const dinr_geometry* geom, const dinr_mlp* mlp, const dinr_sampl
                 const float* B_host, size_t workspace_budget, dinr_ctx** out);
 
 int dinr_destroy(dinr_ctx* ctx);
+
+/* Second key word of the random sample positions (sampling.jitter = 1) for
+ * the calls enqueued after this one; 0 at creation.  No effect on midpoint
+ * sampling.  Returns DINR_EINVAL for a null context. */
+int dinr_set_sample_epoch(dinr_ctx* ctx, uint32_t epoch);
 
 /* Message of the last error on this context (static storage of the context). */
 const char* dinr_last_error(const dinr_ctx* ctx);

@@ -19,6 +19,7 @@ struct dinr_ctx {
   dinr_geometry geom{};
   dinr_mlp mlp{};
   dinr_sampling samp{};
+  uint32_t epoch = 0;  // second key word of the sample-position generator
   int IN = 0, H = 0, L = 0, prec = 0, tile = 0, nmax = 0;
   int64_t np = 0, nh = 0;
   std::vector<int64_t> w_off, b_off;

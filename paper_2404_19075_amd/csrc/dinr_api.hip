@@ -175,6 +175,9 @@ static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
   a.L = c->L;
   a.out_act = c->mlp.out_act;
   a.act = c->mlp.act == DINR_SWISH ? 1 : 0;
+  a.jitter = c->samp.jitter != 0;
+  a.key0 = c->samp.seed;
+  a.key1 = c->epoch;
   a.tile_begin = 0;
   a.tile_end = p.n_tiles_max;
   a.part = p.part;
@@ -331,6 +334,7 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
       break;
     }
     if (s->sub < 0 || s->sub > 8) { rc = bad("rays per projection: D must be in [1, 8]"); break; }
+    if (s->jitter != 0 && s->jitter != 1) { rc = bad("jitter must be 0 or 1"); break; }
     for (int k = 0; k < 4 * m->n_freq; ++k)
       if (!std::isfinite(B_host[k])) { rc = bad("B has a non-finite entry"); break; }
     if (rc) break;
@@ -461,6 +465,12 @@ int dinr_destroy(dinr_ctx* c) {
 }
 
 const char* dinr_last_error(const dinr_ctx* c) { return c ? c->err : "null context"; }
+
+int dinr_set_sample_epoch(dinr_ctx* c, uint32_t epoch) {
+  if (!c) return DINR_EINVAL;
+  c->epoch = epoch;
+  return DINR_OK;
+}
 
 int dinr_profile_enable(dinr_ctx* c, int enable) {
   if (!c) return DINR_EINVAL;

@@ -96,14 +96,38 @@ __host__ __device__ constexpr int chunks(int F) {
 }
 
 // Per-ray record written by the ray-setup kernel.  Coordinates are already
-// normalised to [-1,1]: point j of the ray is  pbar + (s_in + (j+1/2) dl) dbar
-// and its normalised time is tn.  wgt = mu0 l / n (Eq. (1), (2)).
+// normalised to [-1,1]: point j of the ray is  pbar + (s_in + (j+u_j) dl) dbar,
+// u_j = 1/2 or a stratified random offset, and its normalised time is tn.
+// wgt = mu0 l / |Phi| (Eq. (1), (2), Appendix A).  ctr1..ctr3: words 1-3 of
+// the position generator's counter (ray k in its projection, projection
+// index low and high word).
 struct __align__(16) RayRec {
   float px, py, pz, s_in;
   float dx, dy, dz, dl;
   float tn, wgt;
   int32_t n;
   int32_t flags;  // 1: index out of range
+  uint32_t ctr1, ctr2, ctr3, pad;
 };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32 x 32 -> 64-bit products with multipliers 0xD2511F53 and 0xCD9E8D57, the
+// key advanced by 0x9E3779B9 and 0xBB67AE85 after every round.  Returns the
+// first output word, the only one the sample offsets use.
+__device__ inline uint32_t philox_word0(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                        uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, x0), lo0 = 0xD2511F53u * x0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, x2), lo1 = 0xCD9E8D57u * x2;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return x0;
+}
 
 }  // namespace dinr

@@ -74,6 +74,8 @@ struct MlpArgs {
   int64_t wpk_bytes, wtpk_bytes;  // sizes of the packed weight arrays
   int L, out_act;
   int act;                          // hidden activation: 0 ReLU, 1 Swish
+  int jitter;                       // 1: stratified random sample positions
+  uint32_t key0, key1;              // their generator's key (seed, epoch)
   int64_t tile_begin, tile_end;
   // forward outputs
   float* part;               // [2 n_tiles] partial ray-sums

@@ -114,6 +114,7 @@ __device__ inline RayRec make_ray(const GeomDev& g, float u, float v, float c, f
   rec.wgt = (n > 0) ? g.mu0 * len / (float)(n_phi > 0 ? n_phi : n) : 0.f;
   rec.n = n;
   rec.flags = 0;
+  rec.ctr1 = rec.ctr2 = rec.ctr3 = rec.pad = 0u;
   return rec;
 }
 
@@ -136,6 +137,7 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     rec.wgt = 0.f;
     rec.n = 0;
     rec.flags = 1;
+    rec.ctr1 = rec.ctr2 = rec.ctr3 = rec.pad = 0u;
     for (int k = 0; k < D2; ++k) {
       rays[r * D2 + k] = rec;
       nray[r * D2 + k] = 0;
@@ -149,8 +151,12 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
   const int col = (int)(pix - (int64_t)row * g.cols);
   const float u = ((float)col - 0.5f * (float)(g.cols - 1)) * g.pitch_u + g.off_u;
   const float v = ((float)row - 0.5f * (float)(g.rows - 1)) * g.pitch_v + g.off_v;
+  const uint32_t i_lo = (uint32_t)((uint64_t)i & 0xFFFFFFFFu), i_hi = (uint32_t)((uint64_t)i >> 32);
   if (D == 1) {
-    const RayRec rec = make_ray(g, u, v, g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode, g.samp_n);
+    RayRec rec = make_ray(g, u, v, g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode, g.samp_n);
+    rec.ctr1 = 0u;
+    rec.ctr2 = i_lo;
+    rec.ctr3 = i_hi;
     rays[r] = rec;
     nray[r] = rec.n;
     if (n_out) n_out[r] = rec.n;
@@ -164,8 +170,11 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     n_phi += make_ray(g, sub_u(k), sub_v(k), g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode,
                       g.samp_n).n;
   for (int k = 0; k < D2; ++k) {
-    const RayRec rec = make_ray(g, sub_u(k), sub_v(k), g.cth[m], g.sth[m], g.tnorm[m],
-                                g.samp_mode, g.samp_n, n_phi);
+    RayRec rec = make_ray(g, sub_u(k), sub_v(k), g.cth[m], g.sth[m], g.tnorm[m], g.samp_mode,
+                          g.samp_n, n_phi);
+    rec.ctr1 = (uint32_t)k;
+    rec.ctr2 = i_lo;
+    rec.ctr3 = i_hi;
     rays[r * D2 + k] = rec;
     nray[r * D2 + k] = rec.n;
   }
@@ -844,7 +853,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
           if (a.off[mid] <= p) lo = mid; else hi = mid - 1;
         }
         const RayRec rr = a.rays[lo];
-        const float s = rr.s_in + ((float)(p - a.off[lo]) + 0.5f) * rr.dl;
+        const int j = (int)(p - a.off[lo]);
+        // midpoint, or a uniform offset in [0, 1) drawn for (j, ray, projection)
+        float u = 0.5f;
+        if (a.jitter)
+          u = (float)(philox_word0((uint32_t)j, rr.ctr1, rr.ctr2, rr.ctr3, a.key0, a.key1) >> 8) *
+              (1.0f / 16777216.0f);
+        const float s = rr.s_in + ((float)j + u) * rr.dl;
         rt = rr.tn;
         rz = rr.pz + s * rr.dz;
         ry = rr.py + s * rr.dy;

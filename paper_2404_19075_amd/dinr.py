@@ -46,7 +46,7 @@ class MLP(C.Structure):
 class Sampling(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n", C.c_int32), ("n_min", C.c_int32),
                 ("n_max", C.c_int32), ("h", C.c_double), ("sub", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("jitter", C.c_int32), ("seed", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Request(C.Structure):
@@ -64,7 +64,7 @@ EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
            "dinr_profile_enable", "dinr_profile_read", "dinr_server_create", "dinr_server_destroy",
            "dinr_query", "dinr_poll", "dinr_query_wait", "dinr_query_release",
-           "dinr_server_stats", "dinr_probe_mfma"]
+           "dinr_server_stats", "dinr_probe_mfma", "dinr_set_sample_epoch"]
 QUERY_SLICE, QUERY_REPROJECTION = 0, 1
 PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
 
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
     L.dinr_destroy.restype = i32
     L.dinr_last_error.argtypes = [vp]
     L.dinr_last_error.restype = C.c_char_p
+    L.dinr_set_sample_epoch.argtypes = [vp, C.c_uint32]
+    L.dinr_set_sample_epoch.restype = C.c_int
     L.dinr_num_params.argtypes = [vp]
     L.dinr_num_params.restype = i64
     L.dinr_forward_project.argtypes = [vp, vp, vp, i64, vp, vp, vp]
@@ -164,6 +166,8 @@ class Context:
         s.mode, s.n, s.n_min, s.n_max, s.h = (sampling.mode, sampling.n, sampling.n_min,
                                               sampling.n_max, sampling.h)
         s.sub = getattr(sampling, "sub", 1)
+        s.jitter = getattr(sampling, "jitter", 0)
+        s.seed = getattr(sampling, "seed", 0)
         Bh = np.ascontiguousarray(np.asarray(B, dtype=np.float32))
         h = C.c_void_p()
         rc = L.dinr_create(C.byref(g), C.byref(m), C.byref(s),
@@ -190,6 +194,10 @@ class Context:
     def _check(self, rc: int):
         if rc != OK:
             raise DinrError(rc, self._lib.dinr_last_error(self._h).decode())
+
+    def set_sample_epoch(self, epoch: int):
+        """Key word of the random sample positions for the following calls."""
+        self._check(self._lib.dinr_set_sample_epoch(self._h, int(epoch) & 0xFFFFFFFF))
 
     def forward_project(self, params, idx, proj=None, n_out=None):
         """pbar [R] (FP32 device tensor) for projection indices idx (int64)."""

@@ -27,8 +27,10 @@ TOL_PROJ = {FP32: 1e-4, BF16: 2e-2}
 TOL_GRAD = {FP32: 1e-3, BF16: 5e-2}
 
 
-def run_forward(w, batch, prec):
+def run_forward(w, batch, prec, epoch=None):
     ctx = make_ctx(w, batch.B, prec)
+    if epoch is not None:
+        ctx.set_sample_epoch(epoch)
     P = torch.tensor(batch.params, device="cuda")
     idx = torch.tensor(batch.idx, device="cuda")
     n = torch.empty(len(batch.idx), dtype=torch.int32, device="cuda")
@@ -39,8 +41,10 @@ def run_forward(w, batch, prec):
     return out
 
 
-def run_step(w, batch, prec, adam=None, recompute=False):
+def run_step(w, batch, prec, adam=None, recompute=False, epoch=None):
     ctx = make_ctx(w, batch.B, prec, recompute=recompute)
+    if epoch is not None:
+        ctx.set_sample_epoch(epoch)
     P = torch.tensor(batch.params, device="cuda")
     idx = torch.tensor(batch.idx, device="cuda")
     meas = torch.tensor(batch.meas, device="cuda")
@@ -434,3 +438,50 @@ def test_subpixel_rays_cone_variable_counts(prec):
         loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas)
         log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e}")
         check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 D=2 prec={prec}")
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_random_sample_positions_c0(prec):
+    """Stratified random positions (Sec. IV) drawn from Philox4x32-10 on both
+    sides: forward, the one-pass step and the two-pass step match the oracle
+    at the same (seed, epoch); another epoch moves the samples."""
+    w0 = S.workload("c0")
+    w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, jitter=1, seed=2024))
+    b = S.make_batch(w)
+    spe = dataclasses.replace(w.sampling, epoch=5)
+    log(f"test_random_sample_positions_c0 prec={prec}")
+    proj_g, _ = run_forward(w, b, prec, epoch=5)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, spe, b.B, b.params, b.idx)
+    mid, _, _, _ = O.forward(w.geom, w.mlp, w0.sampling, b.B, b.params, b.idx)
+    ep = rel(proj_g, ref)
+    log(f"  forward rel err {ep:.3e} (midpoints differ by {rel(mid, ref):.3e})")
+    assert ep <= TOL_PROJ[prec]
+    assert rel(mid, ref) > 10 * ep
+    loss, grad, proj = O.step(w.geom, w.mlp, spe, b.B, b.params, b.idx, b.meas)
+    for recompute in (False, True):
+        out = run_step(w, b, prec, recompute=recompute, epoch=5)
+        ep2 = rel(out["proj"], proj)
+        log(f"  step recompute={recompute}: proj {ep2:.3e} loss gpu {out['loss']:.6e} "
+            f"oracle {loss:.6e}")
+        assert ep2 <= TOL_PROJ[prec]
+        check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"jitter recompute={recompute}")
+    p6, _ = run_forward(w, b, prec, epoch=6)
+    p5, _ = run_forward(w, b, prec, epoch=5)
+    assert np.array_equal(p5, proj_g) and not np.array_equal(p6, proj_g)
+
+
+def test_random_positions_subpixel_cone_bf16():
+    """Random positions with D = 2 and per-ray counts on the c3 cone beam."""
+    w0 = small_workload("c3", 32)
+    w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, sub=2, jitter=1,
+                                                             seed=99))
+    b = S.make_batch(w)
+    proj_g, n_g = run_forward(w, b, BF16, epoch=3)
+    spe = dataclasses.replace(w.sampling, epoch=3)
+    ref, n_ref, _, _ = O.forward(w.geom, w.mlp, spe, b.B, b.params, b.idx)
+    same = n_g == n_ref.reshape(-1, 4).sum(axis=1)
+    log(f"  count mismatches {int((~same).sum())}")
+    assert same.mean() > 0.9
+    ep = rel(proj_g[same], ref[same])
+    log(f"  proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[BF16]
