@@ -231,6 +231,31 @@ def errors_vs_oracle(batch, ref, n_rays, ws_bytes):
     return out
 
 
+def inference_volume(batch, params_np, n=256, nz=256, n_times=8):
+    """The trained field voxelised on an n x n x nz grid at n_times view times,
+    streamed to a temporary file (Sec. IV inference), BF16."""
+    import tempfile
+    import torch
+    from paper_2404_19075_amd import dinr
+    w = batch.workload
+    ctx = dinr.Context(w.geom, w.mlp, w.sampling, batch.B, precision=dinr.BF16,
+                       workspace_bytes=64 << 20)
+    P = torch.tensor(params_np, device="cuda")
+    srv = dinr.Server(ctx, P, mem_budget=1 << 30, max_active=64)
+    times = [float(t) for t in np.asarray(w.geom.time)[:: max(1, len(w.geom.time) // n_times)][:n_times]]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "volume.bin")
+        srv.write_volume(path, 64, 4, times[:1], slots=4)  # warm-up
+        st = srv.write_volume(path, n, nz, times, slots=8)
+    srv.close()
+    ctx.close()
+    out = dict(grid=f"{n}x{n}x{nz} at {len(times)} view times", voxels=n * n * nz * len(times),
+               bytes=st["bytes"], seconds=st["seconds"], voxels_per_s=st["voxels_per_s"],
+               gb_per_s=st["bytes"] / st["seconds"] / 1e9)
+    log(f"inference volume: {json.dumps(out)}")
+    return out
+
+
 def alg_flops(spec, P_pts):
     """Algorithmic FLOP per step of each kernel class: the forward GEMMs, the
     adjoint's input-gradient GEMMs (a recomputing backward kernel's repeat of
@@ -275,6 +300,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the query-serving run")
     ap.add_argument("--no-paper-net", action="store_true",
                     help="skip the step of the paper's Swish network")
+    ap.add_argument("--no-volume", action="store_true",
+                    help="skip the 4D inference volume written to disk")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale the memory "
                          "counters of a profiler run) and exit")
@@ -342,6 +369,7 @@ def main():
     roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
     paper = None if args.no_paper_net else paper_network(max(2, args.steps // 2), 1, ws)
+    volume = None if args.no_volume else inference_volume(batch, trained)
     cpu, vs_oracle = None, None
     if not args.no_cpu:
         cpu, ref = cpu_baseline(batch)
@@ -370,6 +398,7 @@ def main():
         "fp32": fp32,
         "serving": serve,
         "paper_network": paper,
+        "inference_volume": volume,
         "p50_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p50_ms"],
         "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],
         "roofline": roof,

@@ -42,7 +42,8 @@ enum {
   DINR_ENOMEM = -2,      /* workspace budget too small, or allocation failed */
   DINR_EHIP = -3,        /* a HIP runtime call failed */
   DINR_ENONFINITE = -4,  /* loss or gradient norm is not finite; Adam skipped */
-  DINR_EBUSY = -5        /* serving: admission refused (budget or slots full) */
+  DINR_EBUSY = -5,       /* serving: admission refused (budget or slots full) */
+  DINR_EIO = -6          /* volume writer: the output file could not be written */
 };
 
 enum { DINR_PARALLEL = 0, DINR_CONE = 1 };
@@ -257,6 +258,42 @@ int dinr_query_wait(dinr_server* srv, uint64_t ticket);
 
 /* Forget a completed request's record. */
 int dinr_query_release(dinr_server* srv, uint64_t ticket);
+
+/* 4D inference volume (Sec. IV: the trained field voxelised at a list of
+ * time instants, written to disk as it is produced).  Voxel (t, k, i, j) is
+ * mu0 M at time times[t], height z_k = z0 + (k + 1/2)(z1 - z0)/nz over the FOV's
+ * z extent, and slice pixel (i, j) as in DINR_QUERY_SLICE (cell centres of an
+ * n x n grid over the FOV's x, y extent).  The file holds a 64-byte header
+ * (magic "DINR4DV1", then little-endian int64 nt, nz, n (rows, y), n (columns,
+ * x), zero padding), the nt times as float64, then float32 voxels in the order
+ * [t][z][y][x].  Slices are computed through the server (sharing it with any
+ * other requests), copied to pinned host buffers on a copy stream and written
+ * by a writer thread, `slots` slices in flight, so the GPU, the copy engine
+ * and the disk overlap. */
+typedef struct {
+  int32_t n;            /* slice size n x n */
+  int32_t nz;           /* slices per time instant */
+  int32_t nt;           /* time instants */
+  int32_t slots;        /* slices in flight (device and pinned buffers); 0: 4 */
+  const double* times;  /* host [nt] */
+} dinr_volume;
+
+/* Bytes written, wall-clock seconds of the whole call, and voxels per second
+ * (all nullable in the sense that the struct pointer may be NULL). */
+typedef struct {
+  int64_t bytes;
+  double seconds;
+  double voxels_per_s;
+} dinr_volume_stats;
+
+/* Writes the volume to `path` (created or truncated).  Allocates its slot
+ * buffers (4 n^2 bytes each on the device and in pinned host memory) and frees
+ * them before returning; blocks until the file is complete.  DINR_EINVAL for
+ * a malformed description, DINR_ENOMEM if a slice exceeds the server budget
+ * or the buffers cannot be allocated, DINR_EIO if the file cannot be opened or
+ * written, DINR_EBUSY if the server stops meanwhile. */
+int dinr_volume_write(dinr_server* srv, const dinr_volume* vol, const char* path,
+                      dinr_volume_stats* stats);
 
 /* Counters: kernel launches, tiles run, bytes of admitted outputs, queued
  * and admitted requests (all nullable). */

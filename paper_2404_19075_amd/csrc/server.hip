@@ -20,6 +20,8 @@
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <thread>
@@ -375,6 +377,161 @@ int dinr_server_stats(dinr_server* s, int64_t* launches, int64_t* tiles, size_t*
   if (queued) *queued = (int32_t)s->queue.size();
   if (admitted) *admitted = (int32_t)s->active.size();
   return DINR_OK;
+}
+
+int dinr_volume_write(dinr_server* s, const dinr_volume* v, const char* path,
+                      dinr_volume_stats* stats) {
+  if (!s) return DINR_EINVAL;
+  dinr_ctx* c = s->ctx;
+  if (!v || !path || !v->times) return fail(c, DINR_EINVAL, "null volume description");
+  if (v->n < 1 || v->n > 8192 || v->nz < 1 || v->nt < 1 || v->slots < 0 || v->slots > 64)
+    return fail(c, DINR_EINVAL, "volume: n in [1, 8192], nz, nt >= 1, slots in [0, 64]");
+  for (int t = 0; t < v->nt; ++t)
+    if (!std::isfinite(v->times[t])) return fail(c, DINR_EINVAL, "volume: non-finite time");
+  const int slots = v->slots ? v->slots : 4;
+  const int64_t n2 = (int64_t)v->n * v->n;
+  const size_t bytes = (size_t)n2 * sizeof(float);
+  if (bytes > s->budget) return fail(c, DINR_ENOMEM, "volume: a slice exceeds the server budget");
+  const double t_start = now_ms();
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(c, DINR_EIO, "volume: cannot open %s", path);
+  {
+    char h[64] = {0};
+    std::memcpy(h, "DINR4DV1", 8);
+    const int64_t dims[4] = {v->nt, v->nz, v->n, v->n};
+    std::memcpy(h + 8, dims, sizeof(dims));
+    if (std::fwrite(h, 1, 64, f) != 64 ||
+        std::fwrite(v->times, sizeof(double), (size_t)v->nt, f) != (size_t)v->nt) {
+      std::fclose(f);
+      return fail(c, DINR_EIO, "volume: header write failed");
+    }
+  }
+  // slot buffers: the server writes dev[k]; the copy stream moves it to host[k]
+  std::vector<float*> dev(slots, nullptr), host(slots, nullptr);
+  std::vector<hipEvent_t> ev(slots, nullptr);
+  hipStream_t cs = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+  for (int k = 0; k < slots && ok; ++k)
+    ok = hipMalloc(&dev[k], bytes) == hipSuccess && hipHostMalloc(&host[k], bytes) == hipSuccess &&
+         hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
+  int rc = ok ? DINR_OK : DINR_ENOMEM;
+  // writer thread: slices leave in submission order
+  std::mutex m;
+  std::condition_variable cv;
+  std::deque<int> ready;
+  std::vector<char> is_free(slots, 1);
+  bool quit = false, io_err = false;
+  std::thread writer([&] {
+    for (;;) {
+      int k;
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return quit || !ready.empty(); });
+        if (ready.empty()) return;
+        k = ready.front();
+        ready.pop_front();
+      }
+      bool bad = hipEventSynchronize(ev[k]) != hipSuccess;
+      if (!bad) bad = std::fwrite(host[k], sizeof(float), (size_t)n2, f) != (size_t)n2;
+      {
+        std::lock_guard<std::mutex> lk(m);
+        if (bad) io_err = true;
+        is_free[k] = 1;
+      }
+      cv.notify_all();
+    }
+  });
+  const GeomDev& g = c->gd;
+  const double z0 = g.fov_kind == DINR_FOV_BOX ? c->geom.fov[4] : c->geom.fov[1];
+  const double z1 = g.fov_kind == DINR_FOV_BOX ? c->geom.fov[5] : c->geom.fov[2];
+  const int64_t total = (int64_t)v->nt * v->nz;
+  std::deque<std::pair<int, uint64_t>> inflight;  // (slot, ticket), submission order
+  int64_t next = 0;
+  while (rc == DINR_OK && (next < total || !inflight.empty())) {
+    while (rc == DINR_OK && next < total && (int)inflight.size() < slots) {
+      int k = -1;
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] {
+          return io_err || std::find(is_free.begin(), is_free.end(), 1) != is_free.end();
+        });
+        if (io_err) {
+          rc = DINR_EIO;
+          break;
+        }
+        k = (int)(std::find(is_free.begin(), is_free.end(), 1) - is_free.begin());
+        is_free[k] = 0;
+      }
+      dinr_request r{};
+      r.kind = DINR_QUERY_SLICE;
+      r.n = v->n;
+      const int64_t it = next / v->nz, kz = next % v->nz;
+      r.z_or_theta = z0 + ((double)kz + 0.5) * (z1 - z0) / v->nz;
+      r.t = v->times[it];
+      uint64_t tk = 0;
+      const int q = dinr_query(s, &r, dev[k], &tk);
+      if (q != DINR_OK) {
+        std::lock_guard<std::mutex> lk(m);
+        is_free[k] = 1;
+        rc = q;
+        break;
+      }
+      inflight.emplace_back(k, tk);
+      ++next;
+    }
+    if (rc != DINR_OK || inflight.empty()) break;
+    const auto [k, tk] = inflight.front();
+    inflight.pop_front();
+    const int w = dinr_query_wait(s, tk);
+    dinr_query_release(s, tk);
+    if (w != DINR_OK) {
+      rc = w;
+      break;
+    }
+    if (hipMemcpyAsync(host[k], dev[k], bytes, hipMemcpyDeviceToHost, cs) != hipSuccess ||
+        hipEventRecord(ev[k], cs) != hipSuccess) {
+      rc = DINR_EHIP;
+      break;
+    }
+    {
+      std::lock_guard<std::mutex> lk(m);
+      ready.push_back(k);
+    }
+    cv.notify_all();
+  }
+  // nothing may still write the slot buffers when they are freed
+  for (const auto& q : inflight) {
+    dinr_query_wait(s, q.second);
+    dinr_query_release(s, q.second);
+  }
+  {
+    std::lock_guard<std::mutex> lk(m);
+    quit = true;
+  }
+  cv.notify_all();
+  writer.join();
+  if (rc == DINR_OK && io_err) rc = DINR_EIO;
+  if (s->st) hipStreamSynchronize(s->st);
+  if (cs) {
+    hipStreamSynchronize(cs);
+    hipStreamDestroy(cs);
+  }
+  for (int k = 0; k < slots; ++k) {
+    if (ev[k]) hipEventDestroy(ev[k]);
+    if (dev[k]) hipFree(dev[k]);
+    if (host[k]) hipHostFree(host[k]);
+  }
+  const long end = std::ftell(f);
+  if (std::fclose(f) != 0 && rc == DINR_OK) rc = DINR_EIO;
+  if (stats) {
+    stats->bytes = end;
+    stats->seconds = (now_ms() - t_start) * 1e-3;
+    stats->voxels_per_s = rc == DINR_OK ? (double)total * n2 / stats->seconds : 0.0;
+  }
+  if (rc == DINR_EIO) return fail(c, DINR_EIO, "volume: write to %s failed", path);
+  if (rc == DINR_ENOMEM) return fail(c, DINR_ENOMEM, "volume: slot buffers");
+  if (rc == DINR_EHIP) return fail(c, DINR_EHIP, "volume: device-to-host copy");
+  return rc;
 }
 
 int dinr_server_destroy(dinr_server* s) {

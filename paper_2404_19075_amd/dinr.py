@@ -16,10 +16,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdinr.so")
 
-OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ENONFINITE, EBUSY, EIO = 0, -1, -2, -3, -4, -5, -6
 FP32, BF16 = 0, 1
 _NAMES = {EINVAL: "DINR_EINVAL", ENOMEM: "DINR_ENOMEM", EHIP: "DINR_EHIP",
-          ENONFINITE: "DINR_ENONFINITE", EBUSY: "DINR_EBUSY"}
+          ENONFINITE: "DINR_ENONFINITE", EBUSY: "DINR_EBUSY", EIO: "DINR_EIO"}
 
 
 class DinrError(RuntimeError):
@@ -64,8 +64,17 @@ EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
            "dinr_profile_enable", "dinr_profile_read", "dinr_server_create", "dinr_server_destroy",
            "dinr_query", "dinr_poll", "dinr_query_wait", "dinr_query_release",
-           "dinr_server_stats", "dinr_probe_mfma", "dinr_set_sample_epoch"]
+           "dinr_server_stats", "dinr_probe_mfma", "dinr_set_sample_epoch", "dinr_volume_write"]
 QUERY_SLICE, QUERY_REPROJECTION = 0, 1
+
+
+class Volume(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nz", C.c_int32), ("nt", C.c_int32), ("slots", C.c_int32),
+                ("times", C.POINTER(C.c_double))]
+
+
+class VolumeStats(C.Structure):
+    _fields_ = [("bytes", C.c_int64), ("seconds", C.c_double), ("voxels_per_s", C.c_double)]
 PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
 
 _lib = None
@@ -121,6 +130,8 @@ def load(path: str = LIB_PATH):
                                     C.POINTER(C.c_size_t), C.POINTER(C.c_int32),
                                     C.POINTER(C.c_int32)]
     L.dinr_server_stats.restype = i32
+    L.dinr_volume_write.argtypes = [vp, C.POINTER(Volume), C.c_char_p, C.POINTER(VolumeStats)]
+    L.dinr_volume_write.restype = i32
     _lib = L
     return L
 
@@ -283,6 +294,16 @@ class Server:
 
     def release(self, ticket: int):
         self._ctx._check(self._lib.dinr_query_release(self._h, ticket))
+
+    def write_volume(self, path: str, n: int, nz: int, times, slots: int = 0) -> dict:
+        """The field on an n x n x nz grid at each time in `times`, streamed to
+        `path` (layout: see dinr_volume_write)."""
+        tt = (C.c_double * len(times))(*[float(t) for t in times])
+        v = Volume(int(n), int(nz), len(times), int(slots), tt)
+        st = VolumeStats()
+        self._ctx._check(self._lib.dinr_volume_write(self._h, C.byref(v), path.encode(),
+                                                     C.byref(st)))
+        return dict(bytes=st.bytes, seconds=st.seconds, voxels_per_s=st.voxels_per_s)
 
     def stats(self):
         a, b, c, d, e = C.c_int64(), C.c_int64(), C.c_size_t(), C.c_int32(), C.c_int32()

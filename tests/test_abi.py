@@ -103,3 +103,5 @@ def test_null_arguments():
     assert L.dinr_forward_project(None, None, None, 0, None, None, None) == dinr.EINVAL
     assert L.dinr_step(None, None, None, 0, None, None, None, None, None, None, None) == dinr.EINVAL
     assert L.dinr_destroy(None) == dinr.OK
+    assert L.dinr_volume_write(None, None, None, None) == dinr.EINVAL
+    assert L.dinr_set_sample_epoch(None, 3) == dinr.EINVAL

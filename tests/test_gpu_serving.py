@@ -183,3 +183,39 @@ def test_swish_slice_matches_oracle_field(prec):
     assert e <= TOL[prec]
     srv.close()
     ctx.close()
+
+
+def test_volume_writer_matches_oracle_field(tmp_path):
+    """The 4D volume (Sec. IV) streamed to disk: header, times, and every voxel
+    against the oracle's field; each slice bitwise equal to a direct query."""
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c0", n_rays=8)
+    w = b.workload
+    ctx, P, srv = server_for(w, b, FP32)
+    n, nz, times = 24, 5, [0.1, 0.55, 0.9]
+    path = tmp_path / "vol.bin"
+    st = srv.write_volume(str(path), n, nz, times, slots=3)
+    raw = path.read_bytes()
+    assert raw[:8] == b"DINR4DV1"
+    assert list(np.frombuffer(raw[8:40], dtype="<i8")) == [len(times), nz, n, n]
+    assert not any(raw[40:64])
+    assert list(np.frombuffer(raw[64:64 + 8 * len(times)], dtype="<f8")) == times
+    vol = np.frombuffer(raw[64 + 8 * len(times):], dtype="<f4").reshape(len(times), nz, n, n)
+    assert st["bytes"] == len(raw) and st["voxels_per_s"] > 0
+    z0, z1 = w.geom.fov[4], w.geom.fov[5]
+    zs = [z0 + (k + 0.5) * (z1 - z0) / nz for k in range(nz)]
+    pts = np.concatenate([slice_points(w.geom, n, z, t) for t in times for z in zs])
+    ref = O.field_points(w.geom, w.mlp, b.B, b.params, pts).reshape(vol.shape)
+    e = rel(vol, ref)
+    log(f"  volume rel err {e:.3e}, {st['voxels_per_s']:.3e} voxels/s")
+    assert e <= TOL[FP32]
+    out = torch.empty(n * n, device="cuda")
+    tk = srv.submit(dinr.QUERY_SLICE, n, zs[2], times[1], out)
+    srv.wait(tk)
+    assert np.array_equal(out.cpu().numpy(), vol[1, 2].ravel())
+    # an unwritable path fails on the host before any slice is computed
+    with pytest.raises(dinr.DinrError) as ei:
+        srv.write_volume(str(tmp_path / "missing" / "vol.bin"), n, nz, times)
+    assert ei.value.code == dinr.EIO
+    srv.close()
+    ctx.close()
