@@ -84,9 +84,8 @@ typedef struct {
  * precision: DINR_FP32 runs the MLP GEMMs on FP32 matrix cores; DINR_BF16
  * runs them on BF16 matrix cores with FP32 accumulation.  Supported shapes:
  * (2C, H) in {(128,64), (256,256)}, 1 <= L <= 10, act in {DINR_RELU, DINR_SWISH}
- * (Swish x sigma(x), the activation of the paper's network; its training steps
- * always take the forward + recomputing backward route and stash one more
- * H-vector per point and layer). */
+ * (Swish x sigma(x), the activation of the paper's network; its adjoint stashes
+ * swish'(z) of every layer, one more H-vector per point and layer). */
 typedef struct {
   int32_t n_freq;     /* C */
   int32_t width;      /* H */

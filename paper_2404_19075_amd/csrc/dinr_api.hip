@@ -559,10 +559,10 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   float* proj = proj_out ? proj_out : p.proj;
-  // the one-pass kernel exists for ReLU networks only
-  // (and for one ray per projection: its tiles must hold whole projections)
-  const bool fused = !c->mlp.recompute && c->mlp.act == DINR_RELU && c->samp.mode == 0 &&
-                     c->tile % c->samp.n == 0 && p.D2 == 1;
+  // one pass when every tile holds whole projections: fixed n dividing the
+  // tile, one ray per projection
+  const bool fused = !c->mlp.recompute && c->samp.mode == 0 && c->tile % c->samp.n == 0 &&
+                     p.D2 == 1;
   if (fused) {
     HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
                           p.tr0, st));

@@ -622,7 +622,10 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 #pragma unroll
     for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
   f32x16 accp[NB];
-  chunk_t act_cur[NEPI], act_nxt[NEPI];  // EPI_DERIV: derivative chunks (blocks ob-1, ob)
+  // EPI_DERIV: derivative chunk k of an output block, loaded at the K-step
+  // where chunk k of the block before is consumed (one block of latency)
+  chunk_t actk[NEPI];
+  const char* ap = (const char*)actp + lane_off((uint32_t)(lane * sizeof(chunk_t)));
 #pragma unroll
   for (int ob = 0; ob < OB; ++ob) {
     if (ob % OBP == 0) {
@@ -655,15 +658,6 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     }
     const chunk_t* __restrict__ Wp =
         (const chunk_t*)(((ob / OBP) & 1) ? sW1 : sW0) + (ob % OBP) * KC * 64;
-    if (EPI == EPI_DERIV) {
-      // derivatives of this block's outputs, used by its epilogue during the
-      // next block (one block of latency to hide)
-      const char* ap = (const char*)actp + lane_off((uint32_t)(lane * sizeof(chunk_t)));
-#pragma unroll
-      for (int k = 0; k < NEPI; ++k)
-        act_nxt[k] = *(const chunk_t*)(ap + ((k / CPO) * chunks<PREC>(H) + ob * CPO + k % CPO) *
-                                                64 * sizeof(chunk_t));
-    }
     f32x16 acc[NB];
     if (epi_forward(EPI)) {
       float bq[16];
@@ -700,17 +694,21 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 #pragma unroll
         for (int k = 0; k < NEPI; ++k)
           if ((k * KC) / NEPI == c)
-            epi_chunk<PREC, H, EPI>(accp, ob - 1, k, y, msk, actp, act_cur, lane);
+            epi_chunk<PREC, H, EPI>(accp, ob - 1, k, y, msk, actp, actk, lane);
+      }
+      if (EPI == EPI_DERIV) {
+#pragma unroll
+        for (int k = 0; k < NEPI; ++k)
+          if ((k * KC) / NEPI == c)
+            actk[k] = *(const chunk_t*)(ap + ((k / CPO) * chunks<PREC>(H) + ob * CPO + k % CPO) *
+                                                 64 * sizeof(chunk_t));
       }
     }
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) accp[nb] = acc[nb];
-    if (EPI == EPI_DERIV)
-#pragma unroll
-      for (int k = 0; k < NEPI; ++k) act_cur[k] = act_nxt[k];
   }
 #pragma unroll
-  for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk, actp, act_cur, lane);
+  for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk, actp, actk, lane);
 }
 
 // ACT: 0 ReLU hidden layers, 1 Swish (derivatives of every layer go through
@@ -762,7 +760,6 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
   // the adjoint needs the ReLU masks (or the Swish derivatives) of the
   // forward layers
-  static_assert(ACT == 0 || MODE != MODE_FUSED, "the fused one-pass mode is ReLU only");
   constexpr int FWD_EPI = ACT == 1 ? (BWD_PART ? EPI_SWISH_D : EPI_SWISH)
                                    : (BWD_PART ? EPI_RELU_MASK : EPI_RELU);
   constexpr int ADJ_EPI = ACT == 1 ? EPI_DERIV : EPI_MASK;
@@ -1605,7 +1602,6 @@ hipError_t launch_expand(const float* g_proj, int64_t R, int D2, float* g_ray, h
 template <int PREC, int IN, int H>
 static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st) {
   const dim3 b(Prec<PREC>::WAVES * 64);
-  if (mode == MODE_FUSED && a.act != 0) return hipErrorInvalidValue;
   if (mode == MODE_FWD && a.act == 0)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FWD, 0>), dim3(grid), b, 0, st, a);
   else if (mode == MODE_FWD)
@@ -1614,8 +1610,10 @@ static hipError_t mlp_impl(int mode, const MlpArgs& a, int grid, hipStream_t st)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD, 0>), dim3(grid), b, 0, st, a);
   else if (mode == MODE_BWD)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_BWD, 1>), dim3(grid), b, 0, st, a);
-  else
+  else if (a.act == 0)
     hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED, 0>), dim3(grid), b, 0, st, a);
+  else
+    hipLaunchKernelGGL((k_mlp<PREC, IN, H, MODE_FUSED, 1>), dim3(grid), b, 0, st, a);
   return hipGetLastError();
 }
 

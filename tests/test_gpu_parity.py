@@ -375,15 +375,17 @@ def test_paper_swish_network_ray_subset(prec):
     check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"paper prec={prec}")
 
 
-def test_swish_recompute_flag_is_the_same_step():
-    """Swish networks always take the two-pass route: the recompute flag
-    changes nothing, bit for bit."""
+def test_swish_fused_pass_matches_recompute_pass():
+    """Swish network: the one-pass step and the two-pass step (forward kernel,
+    loss, recomputing backward) evaluate the same arithmetic per point."""
     w = small_workload("paper", 160)
     b = S.make_batch(w)
     o1 = run_step(w, b, BF16)
     o2 = run_step(w, b, BF16, recompute=True)
+    log(f"  grad rel diff {rel(o1['grad'], o2['grad']):.3e}")
     assert np.array_equal(o1["proj"], o2["proj"])
-    assert np.array_equal(o1["grad"], o2["grad"])
+    assert rel(o1["grad"], o2["grad"]) <= 1e-6
+    assert abs(o1["loss"] - o2["loss"]) <= 1e-12 * o2["loss"]
 
 
 def with_sub(w, D, **samp):
