@@ -299,6 +299,51 @@ def test_full_size_c3_ragged_cone():
     ctx.close()
 
 
+def test_full_size_paper_network_sampled():
+    """The paper's network (Swish, five layers, linear output) on the full c2
+    batch, 65,536 rays x 256 samples, BF16, as the benchmark's second leg runs
+    it (one-pass step; a 64 GiB workspace forces several stash chunks).  The
+    step's projections equal the forward kernel's, 48 sampled projections
+    match the oracle one by one, the loss is the FP64 mean of the GPU's own
+    residuals, and the gradient equals the sum of the two halves' gradients
+    from the recomputing backward pass."""
+    w = S.workload("paper")
+    b = S.make_batch(w)
+    R = len(b.idx)
+    log(f"full paper network: R={R}")
+    ctx = make_ctx(w, b.B, BF16, ws_bytes=64 << 30)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    proj = ctx.forward_project(P, idx)
+    proj2 = torch.empty(R, device="cuda")
+    g, _, loss, _ = ctx.step(P, idx, meas, proj=proj2)
+    torch.cuda.synchronize()
+    assert ctx.step_status() == 0
+    pg = proj.cpu().numpy()
+    assert np.array_equal(pg, proj2.cpu().numpy())
+    e64 = pg.astype(np.float64) - b.meas.astype(np.float64)
+    lref = float(np.mean(e64 * e64))
+    log(f"  loss gpu {loss.item():.9e} host {lref:.9e}")
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    pick = np.random.default_rng(5).choice(R, 48, replace=False)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx[pick])
+    ep = rel(pg[pick], ref)
+    log(f"  sampled proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[BF16]
+    h = R // 2
+    g1 = ctx.project_backward(P, idx[:h].contiguous(),
+                              (2.0 / R) * (proj[:h] - meas[:h]).contiguous())
+    g2 = ctx.project_backward(P, idx[h:].contiguous(),
+                              (2.0 / R) * (proj[h:] - meas[h:]).contiguous())
+    torch.cuda.synchronize()
+    gs = g1.cpu().numpy().astype(np.float64) + g2.cpu().numpy().astype(np.float64)
+    e = rel(gs, g.cpu().numpy().astype(np.float64))
+    log(f"  additivity rel err {e:.3e}")
+    assert e <= 1e-5
+    ctx.close()
+
+
 def test_autograd_function_matches_adjoint():
     from paper_2404_19075_amd import dinr
     w = S.workload("c0")
