@@ -49,6 +49,7 @@ def _create(geom=None, mlp=None, samp=None, B=None, budget=64 << 20):
         m.n_freq, m.width, m.depth, m.act, m.out_act, getattr(m, "precision", 0), m.mu0)
     ss = dinr.Sampling()
     ss.mode, ss.n, ss.n_min, ss.n_max, ss.h = sp.mode, sp.n, sp.n_min, sp.n_max, sp.h
+    ss.sub, ss.jitter, ss.seed = sp.sub, sp.jitter, sp.seed
     Bh = np.ascontiguousarray(B, dtype=np.float32)
     h = C.c_void_p()
     rc = L.dinr_create(C.byref(gs), C.byref(ms), C.byref(ss),
@@ -77,6 +78,9 @@ def _replace(obj, **kw):
     dict(samp=dict(n=0)),
     dict(samp=dict(mode=1, h=0.0)),
     dict(samp=dict(mode=1, h=0.01, n_min=10, n_max=5)),
+    dict(samp=dict(sub=9)),
+    dict(samp=dict(sub=-1)),
+    dict(samp=dict(jitter=2)),
 ])
 def test_create_rejects_invalid_descriptions(change):
     w = S.workload("c0")

@@ -219,3 +219,26 @@ def test_volume_writer_matches_oracle_field(tmp_path):
     assert ei.value.code == dinr.EIO
     srv.close()
     ctx.close()
+
+
+def test_swish_reprojection_matches_oracle_projection():
+    """Reprojections of a Swish network through the server."""
+    from paper_2404_19075_amd import dinr
+    w0 = S.workload("c0")
+    w = dataclasses.replace(w0, mlp=dataclasses.replace(w0.mlp, act=1, out_act=0))
+    b = S.make_batch(w, n_rays=8)
+    ctx, P, srv = server_for(w, b, BF16)
+    n, theta, t = 40, 1.1, 0.25
+    out = torch.empty(n * n, device="cuda")
+    tk = srv.submit(dinr.QUERY_REPROJECTION, n, theta, t, out, samples_per_ray=64)
+    srv.wait(tk)
+    got = out.cpu().numpy()
+    g1 = reprojection_geometry(w.geom, n, theta, t)
+    ref, nref, _, _ = O.forward(g1, w.mlp, S.Sampling(mode=0, n=64), b.B, b.params,
+                                np.arange(n * n))
+    e = rel(got, ref)
+    log(f"  swish reprojection rel err {e:.3e}")
+    assert np.all(got[nref == 0] == 0)
+    assert e <= TOL[BF16]
+    srv.close()
+    ctx.close()
