@@ -52,8 +52,11 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     ref = dict(grad=grad.cpu().numpy().copy(), proj=proj.cpu().numpy().copy(),
                loss=float(loss.item()))
     k = 0
+    jitter = getattr(w.sampling, "jitter", 0)
     for _ in range(warmup):
         k += 1
+        if jitter:
+            ctx.set_sample_epoch(k)  # new random sample positions every step
         ctx.step(P, idx, meas, grad=grad, proj=proj, loss=loss, gnorm=gnorm,
                  adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, k))
     torch.cuda.synchronize()
@@ -65,6 +68,8 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     e0.record(st)
     for _ in range(steps):
         k += 1
+        if jitter:
+            ctx.set_sample_epoch(k)
         ctx.step(P, idx, meas, grad=grad, proj=proj, loss=loss, gnorm=gnorm,
                  adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, k))
     e1.record(st)
@@ -268,16 +273,23 @@ def alg_flops(spec, P_pts):
             "mlp_fused": (f_fwd + f_dx + 2 * shapes[-1][1]) * P_pts, "wgrad": f_dw * P_pts}
 
 
-def paper_network(steps, warmup, ws):
+def paper_network(steps, warmup, ws, sub=1, jitter=0):
     """The paper's own network (Swish hidden layers, linear output, five layers
-    of width 256) on a c2-sized batch: the two-pass BF16 step."""
+    of width 256) on a c2-sized batch, BF16; optionally with D x D rays per
+    projection and stratified random sample positions (App. A, Sec. IV)."""
+    import dataclasses
     from paper_2404_19075_amd import dinr
     from paper_2404_19075_amd import synth as S
-    b = S.make_batch("paper")
-    P_pts = len(b.idx) * b.workload.sampling.n
+    w = S.workload("paper")
+    w = dataclasses.replace(w, sampling=dataclasses.replace(w.sampling, sub=sub, jitter=jitter,
+                                                            seed=17))
+    b = S.make_batch(w)
+    P_pts = len(b.idx) * sub * sub * b.workload.sampling.n
     ms, kern, _, status, _ = run_workload("paper", dinr.BF16, b, steps, warmup, ws)
     alg = alg_flops(b.workload.mlp, P_pts)
-    out = dict(workload="paper network on the c2 geometry: 65536 rays x 256 samples, GRFF "
+    rays = "65536 projections x 256 samples" if sub == 1 else \
+        f"65536 projections x {sub}x{sub} rays x 256 samples, random positions"
+    out = dict(workload=f"paper network on the c2 geometry: {rays}, GRFF "
                         "2C=256 (sigma_s 0.5, sigma_t 0.1), 5 Swish layers of width 256, "
                         "linear output, BF16 MLP GEMMs",
                ms_per_step=ms, value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
@@ -285,7 +297,7 @@ def paper_network(steps, warmup, ws):
                kernels={k: dict(ms_per_step=v["ms_per_step"],
                                 alg_tflops=alg[k] / (v["ms_per_step"] * 1e-3) / 1e12)
                         for k, v in kern.items()})
-    log(f"paper network step {ms:.3f} ms  {json.dumps(out['kernels'])}")
+    log(f"paper network (D={sub}, jitter={jitter}) step {ms:.3f} ms  {json.dumps(out['kernels'])}")
     return out
 
 
@@ -369,6 +381,7 @@ def main():
     roof["traffic"] = traffic_from_profile(dom)
     serve = None if args.no_serving else serving(batch, trained)
     paper = None if args.no_paper_net else paper_network(max(2, args.steps // 2), 1, ws)
+    paper_d2 = None if args.no_paper_net else paper_network(2, 1, ws, sub=2, jitter=1)
     volume = None if args.no_volume else inference_volume(batch, trained)
     cpu, vs_oracle = None, None
     if not args.no_cpu:
@@ -398,6 +411,7 @@ def main():
         "fp32": fp32,
         "serving": serve,
         "paper_network": paper,
+        "paper_network_2x2_random": paper_d2,
         "inference_volume": volume,
         "p50_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p50_ms"],
         "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],

@@ -344,6 +344,45 @@ def test_full_size_paper_network_sampled():
     ctx.close()
 
 
+def test_full_size_paper_network_2x2_random_sampled():
+    """The paper's sampling at full size: 65,536 projections x 2 x 2 rays x 256
+    randomly placed samples on the Swish network (67 M samples, the two-pass
+    step over several stash chunks).  48 sampled projections match the oracle
+    at the same (seed, epoch), the loss is the FP64 mean of the GPU's own
+    residuals, and the step's projections equal the forward's."""
+    w0 = S.workload("paper")
+    w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, sub=2, jitter=1,
+                                                             seed=31))
+    b = S.make_batch(w)
+    R = len(b.idx)
+    ctx = make_ctx(w, b.B, BF16, ws_bytes=96 << 30)
+    ctx.set_sample_epoch(12)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    n = torch.empty(R, dtype=torch.int32, device="cuda")
+    proj = ctx.forward_project(P, idx, n_out=n)
+    proj2 = torch.empty(R, device="cuda")
+    g, _, loss, _ = ctx.step(P, idx, meas, proj=proj2)
+    torch.cuda.synchronize()
+    assert ctx.step_status() == 0
+    pg = proj.cpu().numpy()
+    assert np.array_equal(pg, proj2.cpu().numpy())
+    assert np.all(np.isfinite(g.cpu().numpy()))
+    e64 = pg.astype(np.float64) - b.meas.astype(np.float64)
+    lref = float(np.mean(e64 * e64))
+    log(f"  loss gpu {loss.item():.9e} host {lref:.9e}")
+    assert abs(loss.item() - lref) <= 1e-5 * lref
+    pick = np.random.default_rng(9).choice(R, 48, replace=False)
+    spe = dataclasses.replace(w.sampling, epoch=12)
+    ref, n_ref, _, _ = O.forward(w.geom, w.mlp, spe, b.B, b.params, b.idx[pick])
+    assert np.array_equal(n.cpu().numpy()[pick], n_ref.reshape(48, 4).sum(axis=1))
+    ep = rel(pg[pick], ref)
+    log(f"  sampled proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[BF16]
+    ctx.close()
+
+
 def test_autograd_function_matches_adjoint():
     from paper_2404_19075_amd import dinr
     w = S.workload("c0")
