@@ -711,8 +711,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
   for (int k = 0; k < NEPI; ++k) epi_chunk<PREC, H, EPI>(accp, OB - 1, k, y, msk, actp, actk, lane);
 }
 
-// ACT: 0 ReLU hidden layers, 1 Swish (derivatives of every layer go through
-// a stash in the adjoint modes; the one-pass fused mode is ReLU only)
+// ACT: 0 ReLU hidden layers (their masks stay in LDS), 1 Swish (swish'(z) of
+// every layer goes through the stash in the adjoint modes)
 template <int PREC, int IN, int H, int MODE, int ACT>
 __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   using T = Prec<PREC>;
