@@ -201,13 +201,24 @@ def cpu_baseline(batch, n_rays=1024):
     sub = slice(0, n_rays)
     O.build(force=False)
     threads = O.threads()
+    # one thread on a smaller subset first, for the per-core rate
+    n1 = max(1, n_rays // 16)
+    t1 = time.perf_counter()
+    O.step(w.geom, w.mlp, w.sampling, batch.B, batch.params, batch.idx[:n1], batch.meas[:n1],
+           nthreads=1)
+    dt1 = time.perf_counter() - t1
     t0 = time.perf_counter()
-    ref = O.step(w.geom, w.mlp, w.sampling, batch.B, batch.params, batch.idx[sub], batch.meas[sub])
+    ref = O.step(w.geom, w.mlp, w.sampling, batch.B, batch.params, batch.idx[sub], batch.meas[sub],
+                 nthreads=threads)
     dt = time.perf_counter() - t0
     samples = n_rays * w.sampling.n
+    full = len(batch.idx) * w.sampling.n
     return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
                 sample=f"{n_rays} rays x {w.sampling.n} samples of the same batch, forward + "
-                       f"adjoint in FP64 ({dt:.1f} s)"), ref
+                       f"adjoint in FP64 ({dt:.1f} s)",
+                one_thread_value=n1 * w.sampling.n / dt1,
+                one_thread_sample=f"{n1} rays ({dt1:.1f} s)",
+                full_step_s_extrapolated=full / (samples / dt)), ref
 
 
 def errors_vs_oracle(batch, ref, n_rays, ws_bytes):
