@@ -109,7 +109,8 @@ typedef struct {
  * prediction averages mu0 l M over the samples of all D^2 rays, each weighted
  * by its own ray's chord.  A ray missing the FOV has n = 0; a projection none
  * of whose rays hits it is predicted 0.  D > 1 takes the two-pass training
- * step; the query server always traces one ray per pixel.
+ * step; the query server always traces one ray per pixel with midpoint
+ * samples.
  * jitter = 1 places the samples at random (Sec. IV), stratified: sample j of a
  * ray sits at s_in + (j + u) l / n with u uniform in [0, 1), one draw per
  * sample, so the weights are unchanged.  u = (x0 >> 8) 2^-24 with x0 the first
