@@ -330,9 +330,9 @@ def main():
                          "counters of a profiler run) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU's share of the batch; this build has no multi-GPU "
-              "path (the step would shard by one gradient all-reduce, see DESIGN.md).",
-              file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (the step would shard by "
+              "drawing an independent batch per GPU and averaging the gradients with one "
+              "all-reduce before Adam).", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration > 0:
