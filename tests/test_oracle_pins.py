@@ -319,6 +319,10 @@ def test_param_count_matches_paper():
     for C, H, L, count in rows:
         m = S.MLPSpec(n_freq=int(C), width=int(H), depth=int(L))
         assert O.nparams(m) == int(count) == m.n_params
+    # the "paper" workload is that network
+    mp = S.workload("paper").mlp
+    assert (mp.n_freq, mp.width, mp.depth, mp.act, mp.out_act) == (128, 256, 5, 1, 0)
+    assert O.nparams(mp) == int(rows[0][3])
 
 
 # -------------------------------------------------------------- gradient
