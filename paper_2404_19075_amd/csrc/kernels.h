@@ -139,6 +139,9 @@ hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, v
 hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int grid,
                       hipStream_t st);
 hipError_t launch_query(int prec, int in, int h, const MlpArgs& a, int grid, hipStream_t st);
+// one k_mlp instance (defined in mlp.h, instantiated in mlp_inst.hip)
+template <int PREC, int IN, int H, int MODE, int ACT>
+hipError_t mlp_launch(const MlpArgs& a, int grid, hipStream_t st);
 hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int tile,
                         const float* part, float* proj, hipStream_t st);
 hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,

@@ -1,0 +1,233 @@
+// wgrad.hip -- weight-gradient reduction over the adjoint stash (k_wgrad).
+#include "mlp.h"
+
+namespace dinr {
+
+// ------------------------------------------------------------ dW
+
+// dW_l[o][i] = sum_p delta_l[p][o] h_{l-1}[p][i]  (and db_l = sum_p delta_l[p])
+// over the stash blocks of one split.  The stash holds blocks of 32 points in
+// the register layout of k_mlp; each iteration transposes NBLK blocks through
+// LDS into [feature][point] rows so that both matrix-core operands are read
+// as 16-byte runs of consecutive points (K = points).  The stash chunks of the
+// next iteration are loaded into registers while the current one is reduced.
+// COORDS: the h blocks hold point coordinates (layer 1) and the encoding is
+// re-derived; otherwise they hold h_{l-1} in the register-chunk layout.
+// Threads per weight-gradient workgroup: 16 waves at H = 256 (four per SIMD,
+// each holding a quarter of the 32x32 output tiles, so that twice as many
+// stash loads are in flight per compute unit as with 8 waves), 8 below.
+template <int H>
+__host__ __device__ constexpr int wgrad_threads() { return H >= 256 ? 1024 : 512; }
+
+template <int PREC, int FI, int H, bool COORDS>
+__global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
+  using T = Prec<PREC>;
+  using E = typename T::elem_t;
+  using chunk_t = typename T::chunk_t;
+  constexpr int VPC = T::VPC;
+  constexpr int NBLK = PREC == PREC_BF16 ? 2 : 1;  // 32-point blocks per iteration
+  constexpr int BP = 32 * NBLK;                     // points per iteration
+  static_assert(Prec<PREC>::WAVES * Prec<PREC>::NB % (2 * NBLK) == 0,
+                "a tile holds an even number of whole iterations");
+  constexpr int CHd = chunks<PREC>(H), CHi = chunks<PREC>(FI);
+  constexpr int ROW = BP + 16 / (int)sizeof(E);  // padded row (elements)
+  constexpr int RB = H / 32, CB = FI / 32, NT = RB * CB;
+  constexpr int NTH = wgrad_threads<H>();
+  constexpr int NW = NTH / 64;
+  constexpr int TPW = (NT + NW - 1) / NW;
+  constexpr int QD = NBLK * CHd * 64 / NTH, QH = NBLK * CHi * 64 / NTH;  // chunks per thread
+  static_assert(QD * NTH == NBLK * CHd * 64 && QH * NTH == NBLK * CHi * 64, "chunk split");
+  // two buffer pairs of transposed operands ([feature][point] rows)
+  __shared__ __align__(16) E sD0[H * ROW];
+  __shared__ __align__(16) E sH0[FI * ROW];
+  __shared__ __align__(16) E sD1[H * ROW];
+  __shared__ __align__(16) E sH1[FI * ROW];
+  __shared__ float4 sBr[FI / 2];  // GRFF rows when the h blocks hold coordinates
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, hf = lane >> 5;
+  constexpr int G = NTH / BP;  // threads per point when encoding coordinates
+  static_assert((FI / 2) % G == 0, "encoding rows split evenly over the point's threads");
+  constexpr bool coords = COORDS;
+  if (coords)
+    for (int k = tid; k < FI / 2; k += blockDim.x) sBr[k] = a.Bmat[k];
+
+  const int64_t P = a.off[a.R];
+  const int64_t n_tiles = (P + a.tile - 1) / a.tile;
+  int64_t pend = n_tiles * a.tile;
+  if (pend > a.chunk_p1) pend = a.chunk_p1;
+  const int64_t nblk = (pend - a.chunk_p0) / 32;  // valid 32-point blocks of the chunk
+  const int64_t it0 = (int64_t)blockIdx.x * (a.kb / NBLK);
+  int64_t it1 = it0 + a.kb / NBLK;
+  const int64_t nit = (nblk + NBLK - 1) / NBLK;
+  if (it1 > nit) it1 = nit;
+  if (it0 >= it1) return;
+
+  // tile k of wave w: 2 x 2 blocks of 32x32 tiles when the output divides
+  // that way (each row and column fragment then serves two tiles), else a
+  // strided walk over the tiles
+  constexpr bool BLK2 = TPW == 4 && NW * 4 == NT && RB % 2 == 0 && CB % 2 == 0;
+  auto tile_rc = [&](int k, int& rb, int& cb) -> bool {
+    if (BLK2) {
+      rb = 2 * (w / (CB / 2)) + (k >> 1);
+      cb = 2 * (w % (CB / 2)) + (k & 1);
+      return true;
+    }
+    const int tix = w + NW * k;
+    rb = tix / CB;
+    cb = tix % CB;
+    return tix < NT;
+  };
+  f32x16 acc[TPW];
+#pragma unroll
+  for (int k = 0; k < TPW; ++k)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+  float dbacc = 0.f;
+
+  const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
+  const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
+  const float4* __restrict__ Cst = (const float4*)a.stash + a.h_base;
+  chunk_t cd[QD], ch[QH];
+  float4 rc;  // coordinates of point tid % BP (coordinate mode)
+  // Addresses: a uniform base per iteration plus a 32-bit per-thread byte
+  // offset (kept opaque so it is not widened into 64-bit addresses that are
+  // hoisted, spilled and reloaded between the prefetch loads).
+  const uint32_t toff = lane_off((uint32_t)tid * (uint32_t)sizeof(chunk_t));
+  auto load = [&](int64_t it, chunk_t (&d)[QD], chunk_t (&h)[QH], float4& r) {
+    const char* db = (const char*)(Dst + it * (NBLK * CHd * 64));
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = tid + NTH * k;
+      const bool ok = it * NBLK + q / (CHd * 64) < nblk;
+      d[k] = ok ? *(const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+    }
+    if (coords) {
+      const int p = tid % BP;
+      r = it * NBLK + p / 32 < nblk ? Cst[it * BP + p] : make_float4(0.f, 0.f, 0.f, 0.f);
+      return;
+    }
+    const char* hb = (const char*)(Hst + it * (NBLK * CHi * 64));
+#pragma unroll
+    for (int k = 0; k < QH; ++k) {
+      const int q = tid + NTH * k;
+      const bool ok = it * NBLK + q / (CHi * 64) < nblk;
+      h[k] = ok ? *(const chunk_t*)(hb + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+    }
+  };
+  // Transposition of the registers' iteration into one LDS buffer pair, and
+  // the weight-gradient MFMAs over the other: the two buffers alternate, so
+  // one iteration's transposition overlaps the previous one's MFMAs and each
+  // iteration needs a single barrier.
+  auto transpose = [&](E* tD, E* tH) {
+#pragma unroll
+    for (int k = 0; k < QD; ++k) {
+      const int q = tid + NTH * k;
+      const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
+      const int p = bl * 32 + (l & 31);
+#pragma unroll
+      for (int e = 0; e < VPC; ++e) tD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
+    }
+    if (coords) {
+      // layer 1's input h_0 = [cos 2 pi u ; sin 2 pi u] re-derived exactly as
+      // the forward computed it (App. B item 2)
+      const int p = tid % BP;
+#pragma unroll 4
+      for (int j = tid / BP; j < FI / 2; j += G) {
+        float sv, cv;
+        sincos_rev<PREC>(grff_phase(sBr[j], rc.x, rc.y, rc.z, rc.w), &sv, &cv);
+        tH[j * ROW + p] = (E)cv;
+        tH[(FI / 2 + j) * ROW + p] = (E)sv;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < QH; ++k) {
+        const int q = tid + NTH * k;
+        const int bl = q / (CHi * 64), c = (q / 64) % CHi, l = q & 63;
+        const int p = bl * 32 + (l & 31);
+#pragma unroll
+        for (int e = 0; e < VPC; ++e) tH[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(ch[k], e);
+      }
+    }
+  };
+  auto contract = [&](const E* tD, const E* tH) {
+    if (tid < H) {
+      float sb = 0.f;
+#pragma unroll
+      for (int p = 0; p < BP; ++p) sb += (float)tD[tid * ROW + p];
+      dbacc += sb;
+    }
+    // K-step outer, tiles inner: a wave's tiles share their row and column
+    // fragments (2 x 2 blocks), which are read from LDS once per step
+    constexpr int KS = PREC == PREC_BF16 ? BP / 16 : 4;
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+#pragma unroll
+      for (int k = 0; k < TPW; ++k) {
+        int rb, cb;
+        if (tile_rc(k, rb, cb)) {
+          const E* ra = tD + (32 * rb + (lane & 31)) * ROW;
+          const E* rbp = tH + (32 * cb + (lane & 31)) * ROW;
+          const int o = PREC == PREC_BF16 ? 16 * st + 8 * hf : 16 * hf + 4 * st;
+          T::mma(acc[k], *(const chunk_t*)(ra + o), *(const chunk_t*)(rbp + o));
+        }
+      }
+    }
+  };
+  auto clamp_it = [&](int64_t i) { return i < it1 ? i : it1 - 1; };
+  load(it0, cd, ch, rc);
+  transpose(sD0, sH0);
+  load(clamp_it(it0 + 1), cd, ch, rc);
+  __syncthreads();
+  // a split's iteration count is even (whole tiles of an even number of
+  // iterations, splits of a.kb / NBLK iterations), so the buffers alternate
+  // in a fixed pattern
+  for (int64_t it = it0; it < it1; it += 2) {
+    transpose(sD1, sH1);  // iteration it + 1 (always within the split)
+    load(clamp_it(it + 2), cd, ch, rc);
+    contract(sD0, sH0);  // iteration it
+    __syncthreads();
+    if (it + 2 < it1) {
+      transpose(sD0, sH0);  // iteration it + 2
+      load(clamp_it(it + 3), cd, ch, rc);
+    }
+    contract(sD1, sH1);  // iteration it + 1
+    __syncthreads();
+  }
+  // partial row of this split: same layout as the hidden part of the gradient
+  float* out = a.wpart + (a.split_base + blockIdx.x) * a.nh;
+#pragma unroll
+  for (int k = 0; k < TPW; ++k) {
+    int rb, cb;
+    if (tile_rc(k, rb, cb)) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
+        out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] = acc[k][r];
+      }
+    }
+  }
+  if (tid < H) out[a.b_off + tid] = dbacc;
+}
+
+#define DINR_SHAPES(X) X(128, 64) X(256, 256)
+
+template <int PREC, int FI, int H, bool COORDS>
+static hipError_t wgrad_impl(const WgArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_wgrad<PREC, FI, H, COORDS>), dim3(grid), dim3(wgrad_threads<H>()), 0, st,
+                     a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
+#define X(I, HH)                                                                  \
+  if (h == HH && fi == I && a.coords)                                             \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH, true>(a, grid, st)    \
+                             : wgrad_impl<PREC_F32, I, HH, true>(a, grid, st);    \
+  if (h == HH && fi == HH && !a.coords)                                           \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, HH, HH, false>(a, grid, st)  \
+                             : wgrad_impl<PREC_F32, HH, HH, false>(a, grid, st);
+  DINR_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace dinr
