@@ -312,8 +312,9 @@ def test_weight_matrix_is_out_by_in():
 
 
 def test_param_count_matches_paper():
-    """The paper's network (2C = 256, L = 5) has the parameter count its
-    compression statement is computed from (golden fixture)."""
+    """The paper's network (2C = 256, L = 5; App. B items 3-4, App. C) has
+    the parameter count derived in the golden fixture, which rounds to the
+    approximately 3 x 10^5 parameters Sec. IV states."""
     with open(os.path.join(GOLDEN, "paper_param_count.txt")) as f:
         rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
     for C, H, L, count in rows:
@@ -323,6 +324,8 @@ def test_param_count_matches_paper():
     mp = S.workload("paper").mlp
     assert (mp.n_freq, mp.width, mp.depth, mp.act, mp.out_act) == (128, 256, 5, 1, 0)
     assert O.nparams(mp) == int(rows[0][3])
+    # Sec. IV: "approximately 3 x 10^5" parameters, to one significant figure
+    assert round(int(rows[0][3]), -5) == 300000
 
 
 # -------------------------------------------------------------- gradient
@@ -465,6 +468,56 @@ def test_adam_first_step_closed_form():
     mm, vv = np.zeros(50), np.zeros(50)
     O.adam(p, gr, mm, vv, 1e-3, 0.9, 0.999, 1e-8, 1)
     np.testing.assert_allclose(p, p0 - 1e-3 * gr / (np.abs(gr) + 1e-8), rtol=0, atol=1e-15)
+
+
+def _adam_run(grads, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, p0=None):
+    """Positions after each of a sequence of oracle Adam steps."""
+    n = grads[0].shape[0]
+    p = np.zeros(n) if p0 is None else p0.copy()
+    mm, vv = np.zeros(n), np.zeros(n)
+    out = []
+    for k, g in enumerate(grads, start=1):
+        O.adam(p, np.ascontiguousarray(g, dtype=np.float64), mm, vv, lr, b1, b2, eps, k)
+        out.append(p.copy())
+    return out
+
+
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    """With the same gradient g at every step, the bias-corrected moments are
+    exactly g and g^2 (m_k = (1 - b1^k) g, v_k = (1 - b2^k) g^2), so every step
+    moves each weight by lr g / (|g| + eps).  A moment recursion without its
+    decay (m += (1 - b1) g) or with b1 and b2 exchanged moves by other amounts
+    from the second step on."""
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal(40) * np.logspace(-3, 2, 40)
+    lr, eps = 1e-3, 1e-8
+    ps = _adam_run([g] * 6, lr=lr, eps=eps)
+    for k, p in enumerate(ps, start=1):
+        np.testing.assert_allclose(p, -k * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+
+
+def test_adam_alternating_gradient_second_step():
+    """Gradients g then -g: m_2 = -(1 - b1)^2 g and v_2 = (1 - b2^2) g^2, so the
+    bias-corrected moments are -(1 - b1)/(1 + b1) g and g^2 and the second
+    step moves by +lr (1 - b1)/(1 + b1) g / (|g| + eps)."""
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(30)
+    lr, b1, b2, eps = 2e-3, 0.8, 0.99, 1e-8
+    p1, p2 = _adam_run([g, -g], lr=lr, b1=b1, b2=b2, eps=eps)
+    np.testing.assert_allclose(p2 - p1, lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + eps),
+                               rtol=1e-10, atol=0)
+
+
+def test_adam_zero_gradient_second_step():
+    """Gradients g then 0: m_2 = b1 (1 - b1) g and v_2 = b2 (1 - b2) g^2, so the
+    second step moves by -lr (b1/(1 + b1)) g / (sqrt(b2/(1 + b2)) |g| + eps):
+    the first moment decays with b1 and the second with b2."""
+    rng = np.random.default_rng(6)
+    g = rng.standard_normal(30)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    p1, p2 = _adam_run([g, np.zeros_like(g)], lr=lr, b1=b1, b2=b2, eps=eps)
+    want = -lr * (b1 / (1 + b1)) * g / (np.sqrt(b2 / (1 + b2)) * np.abs(g) + eps)
+    np.testing.assert_allclose(p2 - p1, want, rtol=1e-10, atol=0)
 
 
 # ------------------------------------- D x D rays per projection (Appendix A)
