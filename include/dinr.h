@@ -175,6 +175,24 @@ int64_t dinr_num_params(const dinr_ctx* ctx);
 int dinr_forward_project(dinr_ctx* ctx, const float* params_d, const int64_t* proj_idx_d,
                          int64_t R, float* proj_out_d, int32_t* n_out_d, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * projections and counts as dinr_forward_project, bit for bit, with the same
+ * arguments, but the call allocates and frees nothing -- its scratch (ray
+ * records, offsets, tile map, tile partials, packed weights) is a static
+ * 32 MiB device array of the library, not the context's workspace.  That
+ * is enough for about 330,000 projections of 256 samples with the
+ * 2C = H = 256, six-layer BF16 network (about 96 bytes per ray of 256
+ * samples plus the packed weights).  A larger batch is refused with
+ * DINR_ENOMEM before anything is enqueued; DINR_EHIP if the array's device
+ * address could not be resolved when the context was created.  Every call
+ * on a device shares that device's array and leaves the last call's contents
+ * in it: calls that overlap in time on one device (from any context or
+ * stream) race. */
+int dinr_forward_project_noalloc(dinr_ctx* ctx, const float* params_d,
+                                 const int64_t* proj_idx_d, int64_t R, float* proj_out_d,
+                                 int32_t* n_out_d, void* stream);
+
 /* Adjoint of dinr_forward_project: given dL/dpbar_r in dproj_d (device FP32
  * [R]), writes dL/dgamma = sum_r dproj_r dpbar_r/dgamma (Eq. (8) with an
  * arbitrary upstream) to grad_out_d (device FP32 [n_params], overwritten).

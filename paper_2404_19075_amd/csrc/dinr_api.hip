@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -65,11 +66,56 @@ bool shape_supported(int in, int h) { return (in == 128 && h == 64) || (in == 25
 
 }  // namespace
 
-static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
-  Arena A{c->arena, c->arena_size};
-  // status and scalars live at the start of the arena
-  c->d_status = A.take<int32_t>(4);
-  c->d_scal = A.take<double>(4);
+// ------------------------------------------------- static device scratch
+//
+// Scratch of dinr_forward_project_noalloc: ray records, offsets, tile map,
+// tile partials and packed weights of one call, in a fixed array of the code
+// object instead of the context's workspace.  Each device holds its own copy
+// from the library's load until the process ends.  In host code `scratch`
+// only names the symbol: its device address comes from hipGetSymbolAddress,
+// looked up once per device by dinr_create with that device current.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev` (the current device), resolved on the
+// first call for that device; nullptr (and the HIP error in *err) if the
+// lookup failed.
+char* scratch_address(int dev, hipError_t* err) {
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();  // keep the failure out of later calls' status
+      ptr = nullptr;
+    }
+    g_scratch_ptr[dev] = (char*)ptr;
+    g_scratch_err[dev] = e;
+    g_scratch_done[dev] = true;
+  }
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+// Bytes at the start of the context's arena holding its status word and FP64
+// scalars (loss, gradient norm); every call's plan is carved after them.
+constexpr size_t ARENA_HEAD = 512;
+
+// Carves the buffers of one call out of `A` (the context's arena after its
+// head, or the library's static scratch).
+static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   p->Rp = R;
   p->D2 = (int64_t)c->gd.sub * c->gd.sub;
   p->R = R * p->D2;
@@ -151,6 +197,10 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
     if (c->mlp.act == DINR_SWISH) base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
   }
   return DINR_OK;
+}
+
+static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p) {
+  return plan_call(c, R, adjoint, p, Arena{c->arena + ARENA_HEAD, c->arena_size - ARENA_HEAD});
 }
 
 static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
@@ -385,6 +435,11 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
     return DINR_EHIP;
   }
   c->n_cu = prop.multiProcessorCount;
+  {
+    // resolve the static scratch of this device now, with it current
+    hipError_t se = hipSuccess;
+    (void)scratch_address(c->device, &se);
+  }
   const int nv = g->n_views;
   std::vector<float> cth(nv), sth(nv), tn(nv);
   for (int v = 0; v < nv; ++v) {
@@ -403,6 +458,8 @@ int dinr_create(const dinr_geometry* g, const dinr_mlp* m, const dinr_sampling* 
     return DINR_ENOMEM;
   }
   c->arena_size = budget;
+  c->d_status = (int32_t*)c->arena;
+  c->d_scal = (double*)(c->arena + 256);
   if (hipMemcpy(c->d_cth, cth.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_sth, sth.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_tn, tn.data(), nv * 4, hipMemcpyHostToDevice) != hipSuccess ||
@@ -517,6 +574,27 @@ int dinr_forward_project(dinr_ctx* c, const float* params, const int64_t* idx, i
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
   return enqueue_forward(c, p, params, idx, proj, n_out, st);
+}
+
+int dinr_forward_project_noalloc(dinr_ctx* c, const float* params, const int64_t* idx, int64_t R,
+                                 float* proj, int32_t* n_out, void* stream) {
+  if (!c) return DINR_EINVAL;
+  if (R < 0 || R > (int64_t)INT32_MAX - 1) return fail(c, DINR_EINVAL, "R out of range");
+  if (R > 0 && (!params || !idx || !proj)) return fail(c, DINR_EINVAL, "null buffer");
+  if (R == 0) return DINR_OK;
+  hipError_t se = hipSuccess;
+  char* base = scratch_address(c->device, &se);
+  if (!base)
+    return fail(c, DINR_EHIP, "static scratch of device %d unavailable: %s", c->device,
+                hipGetErrorString(se));
+  Plan p;
+  int rc = plan_call(c, R, false, &p, Arena{base, STATIC_SCRATCH_BYTES});
+  if (rc)
+    return fail(c, DINR_ENOMEM,
+                "R=%lld needs more than the %zu-byte static scratch of the no-allocation "
+                "forward projection", (long long)R, STATIC_SCRATCH_BYTES);
+  HIPCHK(c, hipSetDevice(c->device));
+  return enqueue_forward(c, p, params, idx, proj, n_out, (hipStream_t)stream);
 }
 
 int dinr_project_backward(dinr_ctx* c, const float* params, const int64_t* idx, int64_t R,

@@ -64,7 +64,8 @@ EXPORTS = ["dinr_create", "dinr_destroy", "dinr_last_error", "dinr_num_params",
            "dinr_forward_project", "dinr_project_backward", "dinr_step", "dinr_step_status",
            "dinr_profile_enable", "dinr_profile_read", "dinr_server_create", "dinr_server_destroy",
            "dinr_query", "dinr_poll", "dinr_query_wait", "dinr_query_release",
-           "dinr_server_stats", "dinr_probe_mfma", "dinr_set_sample_epoch", "dinr_volume_write"]
+           "dinr_server_stats", "dinr_probe_mfma", "dinr_set_sample_epoch", "dinr_volume_write",
+           "dinr_forward_project_noalloc"]
 QUERY_SLICE, QUERY_REPROJECTION = 0, 1
 
 
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     L.dinr_num_params.restype = i64
     L.dinr_forward_project.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.dinr_forward_project.restype = i32
+    L.dinr_forward_project_noalloc.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.dinr_forward_project_noalloc.restype = i32
     L.dinr_project_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
     L.dinr_project_backward.restype = i32
     L.dinr_step.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, C.POINTER(Adam), vp]
@@ -218,6 +221,14 @@ class Context:
             proj = torch.empty(R, dtype=torch.float32, device=idx.device)
         self._check(self._lib.dinr_forward_project(self._h, _ptr(params), _ptr(idx), R, _ptr(proj),
                                                    _ptr(n_out), _stream()))
+        return proj
+
+    def forward_project_noalloc(self, params, idx, proj, n_out=None):
+        """forward_project with the library's static scratch: allocates
+        nothing, so proj (and n_out) must be given."""
+        self._check(self._lib.dinr_forward_project_noalloc(self._h, _ptr(params), _ptr(idx),
+                                                           idx.shape[0], _ptr(proj), _ptr(n_out),
+                                                           _stream()))
         return proj
 
     def project_backward(self, params, idx, dproj, grad=None, gnorm=None):
