@@ -30,15 +30,24 @@ def log(*a):
 
 
 def run_workload(name, prec, batch, steps, warmup, ws_bytes):
+    """Times `steps` training steps (Adam included) after `warmup` untimed ones.
+    Returns (ms per step, per-kernel times, the un-timed reference step's
+    outputs, the step status, the trained parameters, the batch's ray-samples
+    as the device counts them)."""
     import torch
     from paper_2404_19075_amd import dinr
     w = batch.workload
     ctx = dinr.Context(w.geom, w.mlp, w.sampling, batch.B, precision=prec,
-                       workspace_bytes=ws_bytes)
+                       workspace_bytes=ws_bytes, recompute=bool(getattr(w, "recompute", False)))
     dev = torch.device("cuda:0")
     P = torch.tensor(batch.params, device=dev)
     idx = torch.tensor(batch.idx, device=dev)
     meas = torch.tensor(batch.meas, device=dev)
+    # |Phi| of every projection: the ray-samples one step evaluates
+    n_out = torch.empty(len(batch.idx), dtype=torch.int32, device=dev)
+    ctx.forward_project(P, idx, n_out=n_out)
+    torch.cuda.synchronize()
+    points = int(n_out.sum().item())
     grad = torch.empty(ctx.n_params, device=dev)
     proj = torch.empty(len(batch.idx), device=dev)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
@@ -77,24 +86,30 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     ms = e0.elapsed_time(e1) / steps
     kern = {}
     for kind, kname in [(dinr.PROF_MLP_FWD, "mlp_fwd"), (dinr.PROF_MLP_BWD, "mlp_bwd"),
-                        (dinr.PROF_MLP_FUSED, "mlp_fused"), (dinr.PROF_WGRAD, "wgrad")]:
+                        (dinr.PROF_MLP_FUSED, "mlp_fused"), (dinr.PROF_WGRAD, "wgrad"),
+                        (dinr.PROF_RAYS, "ray_setup"), (dinr.PROF_LOSS, "loss"),
+                        (dinr.PROF_REDUCE, "reduce")]:
         t, n = ctx.profile_read(kind)
         if n:
-            kern[kname] = dict(total_ms=t, launches=n, ms_per_step=t / steps)
+            kern[kname] = dict(total_ms=t, launches=n, ms_per_step=t / steps,
+                               launches_per_step=n / steps)
     status = ctx.step_status()
     trained = P.cpu().numpy()
     ctx.close()
-    del P, idx, meas, grad, proj, m, v, P0
+    del P, idx, meas, grad, proj, m, v, P0, n_out
     torch.cuda.empty_cache()
-    return ms, kern, ref, status, trained
+    return ms, kern, ref, status, trained, points
 
 
-def serving(batch, params_np, duration_s=4.0, rates=(0.25, 0.5, 0.9), seed=7):
+def serving(batch, params_np, n_req=1000, rates=(0.1, 0.5, 1.0, 2.0), n_cap=200, seed=7):
     """Continuously batched queries of the trained field (BF16): a 50/50 mix of
     n x n slices (n in 64..512) at random (z, t) and parallel-beam
-    reprojections (n in 128..512, 256 samples per ray) at random (theta, t),
-    arriving as a Poisson stream.  Returns capacity and p50/p99 latency per
-    rate."""
+    reprojections (n in 128..512, 256 samples per ray) at random (theta, t).
+    Capacity is the completion rate of a closed batch of n_cap mixed requests
+    submitted at once; then, at each rate (a fraction of that capacity),
+    n_req requests arrive as a Poisson stream, each with its own output
+    buffer, and the server admits them by its 1 GB output budget and 64 slots.
+    Returns capacity and p50/p99 submit-to-completion latency per rate."""
     import torch
     from paper_2404_19075_amd import dinr
     w = batch.workload
@@ -103,8 +118,7 @@ def serving(batch, params_np, duration_s=4.0, rates=(0.25, 0.5, 0.9), seed=7):
     P = torch.tensor(params_np, device="cuda")
     srv = dinr.Server(ctx, P, mem_budget=1 << 30, max_active=64)
     rng = np.random.default_rng(seed)
-    pool = [torch.empty(512 * 512, device="cuda") for _ in range(64)]
-    busy = [None] * len(pool)
+    pool = [torch.empty(512 * 512, device="cuda") for _ in range(max(n_req, n_cap))]
 
     def draw():
         if rng.random() < 0.5:
@@ -113,70 +127,82 @@ def serving(batch, params_np, duration_s=4.0, rates=(0.25, 0.5, 0.9), seed=7):
         return (dinr.QUERY_REPROJECTION, int(rng.choice([128, 256, 384, 512])),
                 float(rng.uniform(0, 2 * np.pi)), float(rng.uniform(0, 1)), 256)
 
-    def free_slot():
-        # an output buffer whose last request has completed (tickets are
-        # released by whoever collects their latency)
-        while True:
-            for k, tk in enumerate(busy):
-                if tk is None or srv.poll(tk)[0]:
-                    busy[k] = None
-                    return k
-            time.sleep(0.0002)
+    def submit(k, r):
+        return srv.submit(r[0], r[1], r[2], r[3], pool[k], samples_per_ray=r[4])
 
-    # capacity: a closed batch of mixed requests submitted at once
-    reqs = [draw() for _ in range(24)]
+    # warm-up, then capacity: a closed batch of mixed requests submitted at once
+    for tk in [submit(k, draw()) for k in range(8)]:
+        srv.wait(tk)
+        srv.release(tk)
+    reqs = [draw() for _ in range(n_cap)]
     t0 = time.perf_counter()
-    tks = []
-    for r in reqs:
-        k = free_slot()
-        busy[k] = srv.submit(r[0], r[1], r[2], r[3], pool[k], samples_per_ray=r[4])
-        tks.append(busy[k])
+    tks = [submit(k, r) for k, r in enumerate(reqs)]
     for tk in tks:
         srv.wait(tk)
     cap = len(reqs) / (time.perf_counter() - t0)
     for tk in tks:
         srv.release(tk)
-    busy = [None] * len(pool)
-    log(f"serving capacity {cap:.2f} req/s")
-    out = dict(capacity_req_per_s=cap, mix="50% slices n=64..512, 50% reprojections n=128..512 "
-               "x 256 samples", rates=[])
+    log(f"serving capacity {cap:.2f} req/s ({n_cap} requests)")
+    out = dict(capacity_req_per_s=cap, capacity_requests=n_cap,
+               mix="50% slices n=64..512, 50% reprojections n=128..512 x 256 samples",
+               mem_budget_bytes=1 << 30, max_active=64, rates=[])
     for frac in rates:
         rate = frac * cap
-        n_req = max(int(rate * duration_s), 8)
-        gaps = rng.exponential(1.0 / rate, size=n_req)
-        arrivals = np.cumsum(gaps)
-        lat = []
-        pending = []
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+        pending, kinds = [], []
         start = time.perf_counter()
-        for a in arrivals:
+        for k, a in enumerate(arrivals):
             while time.perf_counter() - start < a:
                 time.sleep(0.0002)
             r = draw()
-            k = free_slot()
-            busy[k] = srv.submit(r[0], r[1], r[2], r[3], pool[k], samples_per_ray=r[4])
-            pending.append(busy[k])
+            kinds.append(r[0])
+            pending.append(submit(k, r))
+            if (k + 1) % 250 == 0:
+                log(f"  rate {frac:.2f}x: {k + 1} requests submitted")
+        lat = []
         for tk in pending:
             srv.wait(tk)
             lat.append(srv.poll(tk)[1])
             srv.release(tk)
-        busy = [None] * len(pool)
         span = time.perf_counter() - start
         lat = np.array(lat)
-        row = dict(rate_req_per_s=rate, requests=len(lat), p50_ms=float(np.percentile(lat, 50)),
-                   p99_ms=float(np.percentile(lat, 99)), throughput_req_per_s=len(lat) / span)
+        kinds = np.array(kinds)
+        row = dict(load=frac, rate_req_per_s=rate, requests=len(lat),
+                   p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                   p50_ms_slices=float(np.percentile(lat[kinds == 0], 50)),
+                   p99_ms_slices=float(np.percentile(lat[kinds == 0], 99)),
+                   p50_ms_reprojections=float(np.percentile(lat[kinds == 1], 50)),
+                   p99_ms_reprojections=float(np.percentile(lat[kinds == 1], 99)),
+                   throughput_req_per_s=len(lat) / span)
         log(f"serving rate {rate:.2f}/s: {json.dumps(row)}")
         out["rates"].append(row)
+    st = srv.stats()
+    out["launches"] = st["launches"]
+    out["tiles"] = st["tiles"]
     srv.close()
     ctx.close()
     return out
 
 
+KERNEL_SOURCES = ["dinr_dev.h", "ray_dev.h", "kernels.h", "mlp.h", "mlp_inst.hip", "wgrad.hip",
+                  "kernels.hip"]
+
+
+def kernel_source_digest():
+    """sha256 prefix of the sources that define the step's kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2404_19075_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profile(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
-    when the summary does not cover this build of the kernel."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        "hbm_traffic_c2_bf16.txt")
+    when the summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_c2_bf16.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -184,12 +210,8 @@ def traffic_from_profile(kernel):
         parts = line.split()
         if len(parts) == 2 and not line.startswith("#"):
             vals[parts[0]] = parts[1]
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2404_19075_amd",
-                       "csrc", "kernels.hip")
-    import hashlib
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     key = f"{kernel}_bytes_per_launch"
-    if vals.get("kernels_hip_sha256_16") != digest or key not in vals:
+    if vals.get("kernel_sources_sha256_16") != kernel_source_digest() or key not in vals:
         return None
     return float(vals[key])
 
@@ -213,12 +235,26 @@ def cpu_baseline(batch, n_rays=1024):
     dt = time.perf_counter() - t0
     samples = n_rays * w.sampling.n
     full = len(batch.idx) * w.sampling.n
+    # the whole tiny workload (c0: 1024 rays x 64 samples, the network of
+    # width 64), one full step, on every core and on one
+    from paper_2404_19075_amd import synth as S
+    b0 = S.make_batch("c0")
+    w0 = b0.workload
+    c0 = {}
+    for label, nt in (("all_cores", threads), ("one_thread", 1)):
+        t = time.perf_counter()
+        O.step(w0.geom, w0.mlp, w0.sampling, b0.B, b0.params, b0.idx, b0.meas, nthreads=nt)
+        dtc = time.perf_counter() - t
+        c0[label] = dict(threads=nt, step_s=dtc,
+                         ray_samples_per_s=len(b0.idx) * w0.sampling.n / dtc)
     return dict(value=samples / dt, unit="ray-samples/s", cores=threads, kind="oracle",
                 sample=f"{n_rays} rays x {w.sampling.n} samples of the same batch, forward + "
                        f"adjoint in FP64 ({dt:.1f} s)",
                 one_thread_value=n1 * w.sampling.n / dt1,
                 one_thread_sample=f"{n1} rays ({dt1:.1f} s)",
-                full_step_s_extrapolated=full / (samples / dt)), ref
+                full_step_s_extrapolated=full / (samples / dt),
+                c0_full_step=dict(workload="c0: 1024 rays x 64 samples, GRFF 2C=128, 3 ReLU "
+                                           "layers of width 64, forward + adjoint in FP64", **c0)), ref
 
 
 def errors_vs_oracle(batch, ref, n_rays, ws_bytes):
@@ -272,6 +308,28 @@ def inference_volume(batch, params_np, n=256, nz=256, n_times=8):
     return out
 
 
+def stream_rates(kern, R, D2, points, tile=256):
+    """HBM rates of the ray and projection streams (GB/s), from the bytes
+    each kernel class moves by construction and its HIP-event time.
+    ray setup: the projection index (8 B), then per ray record the record
+    (64 B) and its count (4 B) written, the count read twice and the point
+    offset written by the scan (16 B), and per 256-point tile its first ray
+    (4 B).  loss: per projection the measurement and the prediction (4 B
+    each) and the upstream gradient written (4 B); the one-pass step's loss
+    kernel instead reads each ray record's count and flags (8 B) and the
+    measurement (4 B)."""
+    out = {}
+    n_rec = R * D2
+    tiles = (points + tile - 1) // tile
+    b = dict(ray_setup=R * 8 + n_rec * (64 + 4 + 16) + tiles * 4, loss=R * 12)
+    for k, nbytes in b.items():
+        if k in kern:
+            ms = kern[k]["ms_per_step"]
+            out[k] = dict(ms_per_step=ms, bytes=nbytes, gb_per_s=nbytes / (ms * 1e-3) / 1e9,
+                          launches_per_step=kern[k]["launches_per_step"])
+    return out
+
+
 def alg_flops(spec, P_pts):
     """Algorithmic FLOP per step of each kernel class: the forward GEMMs, the
     adjoint's input-gradient GEMMs (a recomputing backward kernel's repeat of
@@ -295,20 +353,52 @@ def paper_network(steps, warmup, ws, sub=1, jitter=0):
     w = dataclasses.replace(w, sampling=dataclasses.replace(w.sampling, sub=sub, jitter=jitter,
                                                             seed=17))
     b = S.make_batch(w)
-    P_pts = len(b.idx) * sub * sub * b.workload.sampling.n
-    ms, kern, _, status, _ = run_workload("paper", dinr.BF16, b, steps, warmup, ws)
+    ms, kern, _, status, _, P_pts = run_workload("paper", dinr.BF16, b, steps, warmup, ws)
     alg = alg_flops(b.workload.mlp, P_pts)
     rays = "65536 projections x 256 samples" if sub == 1 else \
         f"65536 projections x {sub}x{sub} rays x 256 samples, random positions"
     out = dict(workload=f"paper network on the c2 geometry: {rays}, GRFF "
                         "2C=256 (sigma_s 0.5, sigma_t 0.1), 5 Swish layers of width 256, "
                         "linear output, BF16 MLP GEMMs",
-               ms_per_step=ms, value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
+               ray_samples=P_pts, ms_per_step=ms, value=P_pts / (ms * 1e-3),
+               unit="ray-samples/s", status=status,
                step_tflops=b.workload.mlp.flops_per_point() * P_pts / (ms * 1e-3) / 1e12,
                kernels={k: dict(ms_per_step=v["ms_per_step"],
                                 alg_tflops=alg[k] / (v["ms_per_step"] * 1e-3) / 1e12)
-                        for k, v in kern.items()})
+                        for k, v in kern.items() if k in alg},
+               other_kernels={k: v for k, v in kern.items() if k not in alg})
     log(f"paper network (D={sub}, jitter={jitter}) step {ms:.3f} ms  {json.dumps(out['kernels'])}")
+    return out
+
+
+def cone_ragged(steps, warmup, ws):
+    """The ragged cone-beam workload (c3): 131,072 rays of a 512^2 detector,
+    1800 views, n = clamp(ceil(l/h), 32, 512) samples per ray, 8 ReLU layers
+    of width 256, BF16, the two-pass step recomputing the forward in the
+    backward kernel.  Algorithmic rates leave the recomputed forward out."""
+    from paper_2404_19075_amd import dinr
+    from paper_2404_19075_amd import synth as S
+    t0 = time.perf_counter()
+    b = S.make_batch("c3")
+    log(f"c3 inputs ready in {time.perf_counter() - t0:.1f} s")
+    ms, kern, _, status, _, P_pts = run_workload("c3", dinr.BF16, b, steps, warmup, ws)
+    spec = b.workload.mlp
+    alg = alg_flops(spec, P_pts)
+    f_all = spec.flops_per_point()
+    out = dict(workload="c3: cone beam SOD 500 SDD 1000, 512x512 detector, 1800 views over 360 "
+                        "deg, 131072 rays x clamp(ceil(l*256), 32, 512) samples, GRFF 2C=256, "
+                        "8 ReLU layers of width 256, softplus output, BF16, recomputing backward",
+               rays=len(b.idx), ray_samples=P_pts, ms_per_step=ms,
+               value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
+               step_tflops=f_all * P_pts / (ms * 1e-3) / 1e12,
+               step_frac=f_all * P_pts / (ms * 1e-3) / PEAK["bf16"],
+               kernels={k: dict(ms_per_step=v["ms_per_step"], launches=v["launches"],
+                                alg_tflops=alg[k] / (v["ms_per_step"] * 1e-3) / 1e12,
+                                frac=alg[k] / (v["ms_per_step"] * 1e-3) / PEAK["bf16"])
+                        for k, v in kern.items() if k in alg},
+               streams=stream_rates(kern, len(b.idx), 1, P_pts),
+               other_kernels={k: v for k, v in kern.items() if k not in alg})
+    log(f"c3 step {ms:.3f} ms  {json.dumps(out['kernels'])}")
     return out
 
 
@@ -325,6 +415,11 @@ def main():
                     help="skip the step of the paper's Swish network")
     ap.add_argument("--no-volume", action="store_true",
                     help="skip the 4D inference volume written to disk")
+    ap.add_argument("--no-c3", action="store_true", help="skip the ragged cone-beam step")
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests per arrival rate in the serving sweep")
+    ap.add_argument("--serving-loads", type=str, default="0.1,0.5,1.0,2.0",
+                    help="arrival rates of the serving sweep, as fractions of its capacity")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (to scale the memory "
                          "counters of a profiler run) and exit")
@@ -354,13 +449,13 @@ def main():
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s: R={len(batch.idx)} points={P_pts}")
     ws = int(args.workspace_gb * (1 << 30))
 
-    ms_bf16, kern, ref_bf16, status, trained = run_workload("c2", dinr.BF16, batch, args.steps,
-                                                            args.warmup, ws)
+    ms_bf16, kern, ref_bf16, status, trained, P_pts = run_workload("c2", dinr.BF16, batch,
+                                                                   args.steps, args.warmup, ws)
     log(f"bf16 step {ms_bf16:.3f} ms  kernels {json.dumps(kern)}  status {status}")
     fp32 = None
     if not args.no_fp32:
-        ms_fp32, kern32, ref_fp32, _, _ = run_workload("c1", dinr.FP32, batch,
-                                                       max(2, args.steps // 4), 1, ws)
+        ms_fp32, kern32, ref_fp32, _, _, _ = run_workload("c1", dinr.FP32, batch,
+                                                          max(2, args.steps // 4), 1, ws)
         log(f"fp32 step {ms_fp32:.3f} ms  kernels {json.dumps(kern32)}")
 
         def rel(a, b):
@@ -375,14 +470,19 @@ def main():
     spec = w.mlp
     f_all = spec.flops_per_point()
     alg = alg_flops(spec, P_pts)
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    gemm = {k: v for k, v in kern.items() if k in alg}
+    dom = max(gemm, key=lambda k: gemm[k]["ms_per_step"])
     ach = alg[dom] / (kern[dom]["ms_per_step"] * 1e-3)
     roof = dict(bound="mfma", kernel=dom, achieved=ach / 1e12, peak=PEAK["bf16"] / 1e12,
                 unit="TFLOP/s", frac=ach / PEAK["bf16"], traffic=None,
-                kernels={k: dict(ms_per_step=kern[k]["ms_per_step"],
-                                 alg_tflops=alg[k] / (kern[k]["ms_per_step"] * 1e-3) / 1e12)
-                         for k in kern},
-                step_frac=(f_all * P_pts / (ms_bf16 * 1e-3)) / PEAK["bf16"])
+                kernels={k: dict(ms_per_step=gemm[k]["ms_per_step"],
+                                 alg_tflops=alg[k] / (gemm[k]["ms_per_step"] * 1e-3) / 1e12)
+                         for k in gemm},
+                step_frac=(f_all * P_pts / (ms_bf16 * 1e-3)) / PEAK["bf16"],
+                # the target for the MLP GEMMs: half the dense BF16 peak
+                target_frac=0.5, target_met=bool(ach / PEAK["bf16"] >= 0.5),
+                streams=stream_rates(kern, len(batch.idx), 1, P_pts),
+                other_kernels={k: v for k, v in kern.items() if k not in alg})
     # sustained matrix-core rate of this device: operands in registers, and
     # with the A operand streamed from LDS as in the MLP layers
     probe = dict(mfma_registers=dinr.probe_mfma(0, 20000), mfma_lds_operand=dinr.probe_mfma(1, 20000))
@@ -390,10 +490,13 @@ def main():
     roof["measured_peak_tflops"] = probe
     roof["frac_of_measured_peak"] = roof["achieved"] / max(probe.values())
     roof["traffic"] = traffic_from_profile(dom)
-    serve = None if args.no_serving else serving(batch, trained)
+    loads = tuple(float(x) for x in args.serving_loads.split(","))
+    serve = None if args.no_serving else serving(batch, trained, n_req=args.serving_requests,
+                                                 rates=loads)
     paper = None if args.no_paper_net else paper_network(max(2, args.steps // 2), 1, ws)
     paper_d2 = None if args.no_paper_net else paper_network(2, 1, ws, sub=2, jitter=1)
     volume = None if args.no_volume else inference_volume(batch, trained)
+    cone = None if args.no_c3 else cone_ragged(max(2, args.steps // 4), 1, ws)
     cpu, vs_oracle = None, None
     if not args.no_cpu:
         cpu, ref = cpu_baseline(batch)
@@ -424,8 +527,10 @@ def main():
         "paper_network": paper,
         "paper_network_2x2_random": paper_d2,
         "inference_volume": volume,
-        "p50_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p50_ms"],
-        "p99_ms": None if serve is None else serve["rates"][len(serve["rates"]) // 2]["p99_ms"],
+        "c3": cone,
+        # latency at half the measured capacity
+        "p50_ms": None if serve is None else serve["rates"][min(1, len(loads) - 1)]["p50_ms"],
+        "p99_ms": None if serve is None else serve["rates"][min(1, len(loads) - 1)]["p99_ms"],
         "roofline": roof,
         "cpu_baseline": cpu,
         "vs_oracle_rel_err": vs_oracle,

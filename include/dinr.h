@@ -330,7 +330,11 @@ enum {
   DINR_PROF_MLP_BWD = 1,  /* recomputed forward and adjoint chain, operand stash */
   DINR_PROF_WGRAD = 2,    /* weight-gradient reduction over the stash */
   DINR_PROF_MLP_FUSED = 3, /* one-pass forward, ray-sum, loss terms and adjoint chain */
-  DINR_PROF_KINDS = 4
+  DINR_PROF_RAYS = 4,     /* ray setup: rays of each projection, offset scan, tile map */
+  DINR_PROF_LOSS = 5,     /* residuals, FP64 loss and upstream gradient (with the D x D
+                             bundling of ray sums and spreading of the upstream) */
+  DINR_PROF_REDUCE = 6,   /* compensated cross-split gradient sums and FP64 ||grad||^2 */
+  DINR_PROF_KINDS = 7
 };
 int dinr_profile_enable(dinr_ctx* ctx, int enable);
 int dinr_profile_read(dinr_ctx* ctx, int kind, double* total_ms, int64_t* launches);

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["dinr_api.hip", "kernels.hip", "wgrad.hip", "server.hip", "probe.hip"]
 # the fused MLP kernel is instantiated once per (precision, mode): FP32/BF16 x
-# forward, backward, fused one-pass, query
-MLP_UNITS = [(prec, mode) for prec in (0, 1) for mode in (0, 1, 2, 3)]
+# forward, backward, fused one-pass, query, grouped one-pass
+MLP_UNITS = [(prec, mode) for prec in (0, 1) for mode in (0, 1, 2, 3, 4)]
 LIB = os.path.join(HERE, "libdinr.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 

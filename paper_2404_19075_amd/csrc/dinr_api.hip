@@ -41,6 +41,8 @@ struct Plan {
   int32_t* nray = nullptr;
   int64_t* off = nullptr;
   int32_t* tr0 = nullptr;
+  int64_t* scan_ws = nullptr;  // block sums of the offset scan
+  double* lsum = nullptr;      // per-workgroup partial sums of the loss
   float* part = nullptr;
   float* gup = nullptr;
   float* proj = nullptr;
@@ -128,6 +130,8 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   p->nray = A.take<int32_t>(std::max<int64_t>(R, 1));
   p->off = A.take<int64_t>(R + 1);
   p->tr0 = A.take<int32_t>(p->n_tiles_max + 1);
+  p->scan_ws = A.take<int64_t>(std::max<int64_t>(scan_blocks(R), 1));
+  p->lsum = A.take<double>(LOSS_SCRATCH);
   p->part = A.take<float>(2 * std::max<int64_t>(p->n_tiles_max, 1));
   p->gup = A.take<float>(std::max<int64_t>(R, 1));
   p->proj = A.take<float>(std::max<int64_t>(p->Rp, 1));
@@ -148,7 +152,9 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
 
   // adjoint: split partials for the whole batch, output-layer partials per
   // chunk, then as large a stash chunk as the remaining budget allows.
-  const int64_t k_split = 16384;  // points summed by one weight-gradient workgroup
+  // points summed by one weight-gradient workgroup: 16,384 here (the partials
+  // are allocated for it); raised below once the chunk size is known
+  const int64_t k_split = 16384;
   p->kb = k_split / 32;
   int64_t per_point = 0;  // stash elements per point
   // layer 1's input is stashed as the point's 4 coordinates (16 bytes)
@@ -181,7 +187,13 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
                   (long long)chunk);
     chunk = std::max<int64_t>(quantum, (chunk / 2 + quantum - 1) / quantum * quantum);
   }
-  p->splits_per_chunk = p->chunk_points / k_split;
+  // larger splits (up to 65,536 points) while every chunk still gives each
+  // compute unit a split: fewer partials to write and to combine
+  int64_t ks = k_split;
+  while (ks < 65536 && p->chunk_points % (2 * ks) == 0 && p->chunk_points / (2 * ks) >= c->n_cu)
+    ks *= 2;
+  p->kb = ks / 32;
+  p->splits_per_chunk = p->chunk_points / ks;
   // stash region of each layer: h blocks then delta blocks, in 16-byte chunks
   int64_t base = 0;
   const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
@@ -237,8 +249,11 @@ static MlpArgs mlp_args(dinr_ctx* c, const Plan& p, const float* params) {
 
 static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
                            const int64_t* idx, float* proj, int32_t* n_out, hipStream_t st) {
-  HIPCHK(c, launch_rays(c->gd, idx, p.Rp, p.rays, p.nray, n_out, p.off, c->tile, p.n_tiles_max,
-                        p.tr0, st));
+  {
+    ProfScope ps(c, DINR_PROF_RAYS, st);
+    HIPCHK(c, launch_rays(c->gd, idx, p.Rp, p.rays, p.nray, n_out, p.off, c->tile, p.n_tiles_max,
+                          p.tr0, p.scan_ws, st));
+  }
   HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
                         p.bias, p.wo, st));
   MlpArgs a = mlp_args(c, p, params);
@@ -252,7 +267,10 @@ static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
                          p.grid_mlp, st));
   }
   HIPCHK(c, launch_fixup(p.rays, p.off, p.R, c->tile, p.part, ray_out, st));
-  if (p.D2 > 1) HIPCHK(c, launch_bundle(p.ray_proj, p.Rp, (int)p.D2, proj, st));
+  if (p.D2 > 1) {
+    ProfScope ps(c, DINR_PROF_LOSS, st);
+    HIPCHK(c, launch_bundle(p.ray_proj, p.Rp, (int)p.D2, proj, st));
+  }
   return DINR_OK;
 }
 
@@ -260,15 +278,22 @@ static int enqueue_forward(dinr_ctx* c, const Plan& p, const float* params,
 // MODE_BWD: upstream gradient given in gup, forward recomputed per tile.
 // MODE_FUSED: forward, ray-sums, residuals against meas and the adjoint in
 // one pass; proj receives the predictions and lpart the residual sums.
+// MODE_GROUP: as MODE_FUSED for projections of group_tiles tiles each (the
+// rays padded to n points, n a multiple of the tile).
 static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, const float* gup,
                            float* grad, double* gnorm_out, hipStream_t st, int mode = MODE_BWD,
-                           const float* meas = nullptr, float* proj = nullptr) {
+                           const float* meas = nullptr, float* proj = nullptr,
+                           int group_tiles = 1) {
   const int prec = c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32;
   const int64_t tiles_per_chunk = p.chunk_points / c->tile;
   for (int64_t ch = 0; ch < p.n_chunks; ++ch) {
     MlpArgs a = mlp_args(c, p, params);
     a.tile_begin = ch * tiles_per_chunk;
     a.tile_end = std::min<int64_t>((ch + 1) * tiles_per_chunk, p.n_tiles_max);
+    a.group_tiles = group_tiles;
+    a.tiles_per_ray = group_tiles / (int)p.D2;
+    a.d2 = (int)p.D2;
+    a.n_proj = p.Rp;
     a.gup = gup;
     a.meas = meas;
     a.proj = proj;
@@ -281,7 +306,7 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
     }
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
     {
-      ProfScope ps(c, mode == MODE_FUSED ? DINR_PROF_MLP_FUSED : DINR_PROF_MLP_BWD, st);
+      ProfScope ps(c, mode == MODE_BWD ? DINR_PROF_MLP_BWD : DINR_PROF_MLP_FUSED, st);
       HIPCHK(c, launch_mlp(prec, c->IN, c->H, mode, a, p.grid_mlp, st));
     }
     for (int l = 0; l < c->L; ++l) {
@@ -323,9 +348,13 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
   r.np = c->np;
   r.grad = grad;
   r.gn_part = p.gn_part;
-  if (mode == MODE_FUSED)
-    HIPCHK(c, launch_loss_fused(p.rays, meas, p.R, p.lpart, p.n_chunks * p.grid_mlp, proj,
-                                c->d_scal, st));
+  if (mode == MODE_FUSED || mode == MODE_GROUP) {
+    // the grouped step computed every projection's loss term in the kernel
+    ProfScope ps(c, DINR_PROF_LOSS, st);
+    HIPCHK(c, launch_loss_fused(p.rays, meas, mode == MODE_GROUP ? 0 : p.R, p.lpart,
+                                p.n_chunks * p.grid_mlp, proj, p.lsum, c->d_scal, p.Rp, st));
+  }
+  ProfScope ps(c, DINR_PROF_REDUCE, st);
   HIPCHK(c, launch_reduce(r, c->d_scal + 1, gnorm_out, st));
   return DINR_OK;
 }
@@ -607,8 +636,11 @@ int dinr_project_backward(dinr_ctx* c, const float* params, const int64_t* idx, 
   int rc = plan_call(c, R, true, &p);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
-  HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
-                        p.tr0, st));
+  {
+    ProfScope ps(c, DINR_PROF_RAYS, st);
+    HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
+                          p.tr0, p.scan_ws, st));
+  }
   HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk, p.WTpk,
                         p.bias, p.wo, st));
   if (p.D2 > 1) {
@@ -641,9 +673,34 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   // tile, one ray per projection
   const bool fused = !c->mlp.recompute && c->samp.mode == 0 && c->tile % c->samp.n == 0 &&
                      p.D2 == 1;
-  if (fused) {
-    HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile, p.n_tiles_max,
-                          p.tr0, st));
+  // one pass over groups of tiles, each holding one projection, when its rays
+  // have n samples, n a multiple of the tile (Swish network, linear output:
+  // the adjoint reads the activation derivatives back from the stash), and
+  // the stash chunks hold whole groups
+  const int64_t group = c->samp.mode == 0 ? p.D2 * c->samp.n / c->tile : 0;
+  const bool grouped = !fused && !c->mlp.recompute && c->samp.mode == 0 &&
+                       c->samp.n % c->tile == 0 && c->mlp.act == DINR_SWISH &&
+                       c->mlp.out_act == DINR_OUT_IDENTITY && c->L >= 2 && group >= 2 &&
+                       group <= 64 && (p.chunk_points / c->tile) % group == 0;
+  if (grouped) {
+    {
+      ProfScope ps(c, DINR_PROF_RAYS, st);
+      HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile,
+                            p.n_tiles_max, p.tr0, p.scan_ws, st, c->samp.n));
+    }
+    HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk,
+                          p.WTpk, p.bias, p.wo, st));
+    rc = enqueue_adjoint(c, p, params, nullptr, grad, gnorm, st, MODE_GROUP, meas, proj,
+                         (int)group);
+    if (rc) return rc;
+    if (loss)
+      HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else if (fused) {
+    {
+      ProfScope ps(c, DINR_PROF_RAYS, st);
+      HIPCHK(c, launch_rays(c->gd, idx, R, p.rays, p.nray, nullptr, p.off, c->tile,
+                            p.n_tiles_max, p.tr0, p.scan_ws, st));
+    }
     HIPCHK(c, launch_pack(c->prec == DINR_BF16 ? PREC_BF16 : PREC_F32, p.pk, params, p.Wpk,
                           p.WTpk, p.bias, p.wo, st));
     rc = enqueue_adjoint(c, p, params, nullptr, grad, gnorm, st, MODE_FUSED, meas, proj);
@@ -653,8 +710,11 @@ int dinr_step(dinr_ctx* c, float* params, const int64_t* idx, int64_t R, const f
   } else {
     rc = enqueue_forward(c, p, params, idx, proj, nullptr, st);
     if (rc) return rc;
-    HIPCHK(c, launch_loss(proj, meas, R, p.D2 > 1 ? p.gproj : p.gup, c->d_scal, st));
-    if (p.D2 > 1) HIPCHK(c, launch_expand(p.gproj, R, (int)p.D2, p.gup, st));
+    {
+      ProfScope ps(c, DINR_PROF_LOSS, st);
+      HIPCHK(c, launch_loss(proj, meas, R, p.D2 > 1 ? p.gproj : p.gup, p.lsum, c->d_scal, st));
+      if (p.D2 > 1) HIPCHK(c, launch_expand(p.gproj, R, (int)p.D2, p.gup, st));
+    }
     if (loss)
       HIPCHK(c, hipMemcpyAsync(loss, c->d_scal, sizeof(double), hipMemcpyDeviceToDevice, st));
     rc = enqueue_adjoint(c, p, params, p.gup, grad, gnorm, st);

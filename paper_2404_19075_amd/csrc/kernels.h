@@ -15,7 +15,11 @@ constexpr int MAX_LAYERS = 10;
 // adjoint in one pass (tiles must hold whole rays).
 // QUERY: points of queued requests (slices or reprojection rays) listed in a
 // tile table; outputs mu0 M per point or ray-sums per ray.
-enum { MODE_FWD = 0, MODE_BWD = 1, MODE_FUSED = 2, MODE_QUERY = 3 };
+// GROUP: the one-pass step for projections of several tiles (D x D rays of n
+// samples, n a multiple of the tile): per group of tiles holding one
+// projection, the forward of every tile, the projection's residual, then the
+// adjoint of every tile (Swish networks, linear output).
+enum { MODE_FWD = 0, MODE_BWD = 1, MODE_FUSED = 2, MODE_QUERY = 3, MODE_GROUP = 4 };
 
 // One admitted query (device copy).  kind 0: n x n slice of mu0 M at height
 // zn and time tn (normalised), pixel (i, j) at normalised (x, y) =
@@ -77,6 +81,10 @@ struct MlpArgs {
   int jitter;                       // 1: stratified random sample positions
   uint32_t key0, key1;              // their generator's key (seed, epoch)
   int64_t tile_begin, tile_end;
+  // group mode: tiles per group (one projection), tiles per ray, rays per
+  // projection, projections
+  int group_tiles, tiles_per_ray, d2;
+  int64_t n_proj;
   // forward outputs
   float* part;               // [2 n_tiles] partial ray-sums
   float* proj;               // [R]
@@ -131,9 +139,12 @@ struct RedArgs {
 // R projections -> R D^2 ray records; n_out (nullable) is per projection
 hipError_t launch_bundle(const float* ray_proj, int64_t R, int D2, float* proj, hipStream_t st);
 hipError_t launch_expand(const float* g_proj, int64_t R, int D2, float* g_ray, hipStream_t st);
+// scan_ws: int64 [scan_blocks(R D^2)] of scratch for the offset scan
+int64_t scan_blocks(int64_t n_rec);
+// pad_n > 0: every ray record gets pad_n points (see k_rays)
 hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* rays, int32_t* nray,
                        int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
-                       hipStream_t st);
+                       int64_t* scan_ws, hipStream_t st, int pad_n = 0);
 hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, void* WTpk,
                        float* bias, float* wo, hipStream_t st);
 hipError_t launch_mlp(int prec, int in, int h, int mode, const MlpArgs& a, int grid,
@@ -144,10 +155,14 @@ template <int PREC, int IN, int H, int MODE, int ACT>
 hipError_t mlp_launch(const MlpArgs& a, int grid, hipStream_t st);
 hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int tile,
                         const float* part, float* proj, hipStream_t st);
-hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
-                       hipStream_t st);
+// lsum: double [LOSS_SCRATCH] of scratch for the per-workgroup partial sums
+constexpr int LOSS_SCRATCH = 256;
+hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* lsum,
+                       double* loss, hipStream_t st);
+// loss = (lpart sums + the terms of rays without samples) / n_div
 hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, const double* lpart,
-                             int64_t n_lpart, float* proj, double* loss, hipStream_t st);
+                             int64_t n_lpart, float* proj, double* lsum, double* loss,
+                             int64_t n_div, hipStream_t st);
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce(const RedArgs& a, double* gnorm_ws, double* gnorm_out, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,

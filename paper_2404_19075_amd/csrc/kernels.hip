@@ -6,11 +6,11 @@
 //                sample counts
 //   k_bundle     projection = sum of its rays' weighted sums (D > 1)
 //   k_expand     upstream gradient of each ray = that of its projection (D > 1)
-//   k_scan       exclusive scan of sample counts -> ragged point offsets
+//   k_scan_*     exclusive scan of sample counts -> ragged point offsets
 //   k_tiles      first ray of every point tile
 //   k_pack       FP32 parameters -> matrix-core operand fragments (W and W^T)
 //   k_fixup      ray-sums of rays that cross tile boundaries (compensated)
-//   k_loss       residuals, FP64 loss, upstream gradient 2(pbar-p)/R
+//   k_loss*      residuals, FP64 loss, upstream gradient 2(pbar-p)/R
 //   k_reduce     compensated sum of the split partials, FP64 ||g||^2
 //   k_adam       Adam update guarded by a finiteness check
 #include "dinr_dev.h"
@@ -23,9 +23,13 @@ namespace dinr {
 // One thread per projection: its D x D rays (Appendix A), ray k = b D + a to
 // the centre of sub-pixel (b, a), at records r D^2 + k.  n_out[r] = |Phi_r|,
 // the samples of all of them.
+// pad_n > 0: every ray record is given pad_n points in the point layout
+// (nray), also a ray that misses the field of view or belongs to an invalid
+// index; such rays keep weight 0, so their points add nothing (the grouped
+// one-pass step needs every projection to span the same number of tiles).
 __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
                        RayRec* __restrict__ rays, int32_t* __restrict__ nray,
-                       int32_t* __restrict__ n_out) {
+                       int32_t* __restrict__ n_out, int pad_n) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   const int D = g.sub, D2 = D * D;
@@ -42,7 +46,7 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     rec.ctr1 = rec.ctr2 = rec.ctr3 = rec.pad = 0u;
     for (int k = 0; k < D2; ++k) {
       rays[r * D2 + k] = rec;
-      nray[r * D2 + k] = 0;
+      nray[r * D2 + k] = pad_n;
     }
     if (n_out) n_out[r] = 0;
     return;
@@ -60,7 +64,7 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     rec.ctr2 = i_lo;
     rec.ctr3 = i_hi;
     rays[r] = rec;
-    nray[r] = rec.n;
+    nray[r] = pad_n > 0 ? pad_n : rec.n;
     if (n_out) n_out[r] = rec.n;
     return;
   }
@@ -78,7 +82,7 @@ __global__ void k_rays(GeomDev g, const int64_t* __restrict__ idx, int64_t R,
     rec.ctr2 = i_lo;
     rec.ctr3 = i_hi;
     rays[r * D2 + k] = rec;
-    nray[r * D2 + k] = rec.n;
+    nray[r * D2 + k] = pad_n > 0 ? pad_n : rec.n;
   }
   if (n_out) n_out[r] = n_phi;
 }
@@ -102,30 +106,82 @@ __global__ void k_expand(const float* __restrict__ g_proj, int64_t R, int D2,
   g_ray[q] = g_proj[q / D2];
 }
 
-// Exclusive scan of n[R] into off[R+1] (one workgroup; R is at most a few
-// million, so a single pass of per-thread serial sums is enough).
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ n, int64_t R,
-                                                int64_t* __restrict__ off) {
-  __shared__ int64_t s[1024];
+// Exclusive scan of n[R] into off[R+1] in three launches: every workgroup
+// sums a segment of SCAN_SEG counts, one workgroup scans those sums, then
+// every workgroup scans its segment from its offset.  Each thread owns
+// SCAN_PER consecutive counts.
+constexpr int SCAN_T = 256, SCAN_PER = 16, SCAN_SEG = SCAN_T * SCAN_PER;
+
+__device__ inline int64_t block_incl_scan(int64_t v, int64_t* s) {
   const int t = threadIdx.x;
-  const int64_t per = (R + 1023) / 1024;
-  const int64_t b = t * per, e = (b + per < R) ? b + per : R;
-  int64_t acc = 0;
-  for (int64_t k = b; k < e; ++k) acc += n[k];
-  s[t] = acc;
+  s[t] = v;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int64_t add = (t >= o) ? s[t - o] : 0;
+  for (int o = 1; o < SCAN_T; o <<= 1) {
+    const int64_t add = t >= o ? s[t - o] : 0;
     __syncthreads();
     s[t] += add;
     __syncthreads();
   }
-  int64_t run = s[t] - acc;  // exclusive prefix of this thread's range
-  for (int64_t k = b; k < e; ++k) {
-    off[k] = run;
-    run += n[k];
+  return s[t];
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(const int32_t* __restrict__ n, int64_t R,
+                                                       int64_t* __restrict__ bsum) {
+  __shared__ int64_t s[SCAN_T];
+  const int64_t i0 = (int64_t)blockIdx.x * SCAN_SEG + (int64_t)threadIdx.x * SCAN_PER;
+  int64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k)
+    if (i0 + k < R) acc += n[i0 + k];
+  const int64_t tot = block_incl_scan(acc, s);
+  if (threadIdx.x == SCAN_T - 1) bsum[blockIdx.x] = tot;
+}
+
+// bsum[0..nb) -> exclusive prefix sums in place; *total = their sum (one
+// workgroup: nb is at most 2^31 / SCAN_SEG).
+__global__ __launch_bounds__(1024) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb,
+                                                    int64_t* __restrict__ total) {
+  __shared__ int64_t s[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b = t * per, e = (b + per < nb) ? b + per : nb;
+  int64_t acc = 0;
+  for (int64_t k = b; k < e; ++k) acc += bsum[k];
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t add = (t >= o) ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
   }
-  if (t == 1023) off[R] = s[1023];
+  int64_t run = s[t] - acc;
+  for (int64_t k = b; k < e; ++k) {
+    const int64_t v = bsum[k];
+    bsum[k] = run;
+    run += v;
+  }
+  if (t == 1023) *total = s[1023];
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(const int32_t* __restrict__ n, int64_t R,
+                                                        const int64_t* __restrict__ bsum,
+                                                        int64_t* __restrict__ off) {
+  __shared__ int64_t s[SCAN_T];
+  const int64_t i0 = (int64_t)blockIdx.x * SCAN_SEG + (int64_t)threadIdx.x * SCAN_PER;
+  int32_t v[SCAN_PER];
+  int64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    v[k] = i0 + k < R ? n[i0 + k] : 0;
+    acc += v[k];
+  }
+  int64_t run = bsum[blockIdx.x] + block_incl_scan(acc, s) - acc;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (i0 + k < R) off[i0 + k] = run;
+    run += v[k];
+  }
 }
 
 // tile_ray0[t] = ray holding point t*TILE (R when past the last point).
@@ -230,55 +286,75 @@ __global__ void k_fixup(const RayRec* __restrict__ rays, const int64_t* __restri
   proj[r] = __fmul_rn(rr.wgt, s);
 }
 
-// Loss (Eq. (5)) in FP64 and the upstream gradient g_r = 2 (pbar_r - p_r) / R.
-// One workgroup, fixed summation order.
-__global__ __launch_bounds__(1024) void k_loss(const float* __restrict__ proj,
-                                                const float* __restrict__ meas, int64_t R,
-                                                float* __restrict__ g, double* __restrict__ loss) {
-  __shared__ double s[1024];
+// Loss (Eq. (5)) in FP64 and the upstream gradient g_r = 2 (pbar_r - p_r) / R,
+// in two launches with a fixed order of summation: LOSS_BLOCKS(R) workgroups
+// each sum the squared residuals of a fixed set of rays into lsum[block],
+// then one workgroup adds lsum in order.
+constexpr int LOSS_T = 256, LOSS_MAX_BLOCKS = LOSS_SCRATCH;
+static_assert(LOSS_MAX_BLOCKS <= LOSS_T, "k_loss_total sums the partials with one thread each");
+inline int loss_blocks(int64_t R) {
+  const int64_t b = (R + LOSS_T - 1) / LOSS_T;
+  return (int)(b < 1 ? 1 : b > LOSS_MAX_BLOCKS ? LOSS_MAX_BLOCKS : b);
+}
+
+__device__ inline void block_sum_store(double acc, double* out) {
+  __shared__ double s[LOSS_T];
   const int t = threadIdx.x;
+  s[t] = acc;
+  __syncthreads();
+  for (int o = LOSS_T / 2; o > 0; o >>= 1) {
+    if (t < o) s[t] += s[t + o];
+    __syncthreads();
+  }
+  if (t == 0) *out = s[0];
+}
+
+__global__ __launch_bounds__(LOSS_T) void k_loss(const float* __restrict__ proj,
+                                                  const float* __restrict__ meas, int64_t R,
+                                                  float* __restrict__ g, double* __restrict__ lsum) {
   double acc = 0.0;
   const float inv = 2.0f / (float)R;
-  for (int64_t r = t; r < R; r += 1024) {
+  for (int64_t r = (int64_t)blockIdx.x * LOSS_T + threadIdx.x; r < R;
+       r += (int64_t)gridDim.x * LOSS_T) {
     const float e = proj[r] - meas[r];
     acc += (double)e * (double)e;
     g[r] = inv * e;
   }
-  s[t] = acc;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (t < o) s[t] += s[t + o];
-    __syncthreads();
-  }
-  if (t == 0) *loss = s[0] / (double)R;
+  block_sum_store(acc, lsum + blockIdx.x);
 }
 
 // Loss of the fused pass: the MLP kernel's per-workgroup sums of squared
 // residuals, plus rays that hold no samples (prediction 0, so the residual
-// is the measurement) and rays with an invalid index (NaN).  One workgroup,
-// fixed order.
-__global__ __launch_bounds__(1024) void k_loss_fused(const RayRec* __restrict__ rays,
-                                                      const float* __restrict__ meas, int64_t R,
-                                                      const double* __restrict__ lpart,
-                                                      int64_t n_lpart, float* __restrict__ proj,
-                                                      double* __restrict__ loss) {
-  __shared__ double s[1024];
-  const int t = threadIdx.x;
+// is the measurement) and rays with an invalid index (NaN).
+__global__ __launch_bounds__(LOSS_T) void k_loss_fused(const RayRec* __restrict__ rays,
+                                                        const float* __restrict__ meas, int64_t R,
+                                                        const double* __restrict__ lpart,
+                                                        int64_t n_lpart, float* __restrict__ proj,
+                                                        double* __restrict__ lsum) {
   double acc = 0.0;
-  for (int64_t k = t; k < n_lpart; k += 1024) acc += lpart[k];
-  for (int64_t r = t; r < R; r += 1024) {
-    const RayRec rr = rays[r];
-    if (rr.flags & 1) {
+  const int64_t stride = (int64_t)gridDim.x * LOSS_T;
+  const int64_t t0 = (int64_t)blockIdx.x * LOSS_T + threadIdx.x;
+  for (int64_t k = t0; k < n_lpart; k += stride) acc += lpart[k];
+  for (int64_t r = t0; r < R; r += stride) {
+    const int32_t n = rays[r].n, flags = rays[r].flags;
+    if (flags & 1) {
       proj[r] = __builtin_nanf("");
       acc += (double)__builtin_nanf("");
-    } else if (rr.n == 0) {
+    } else if (n == 0) {
       proj[r] = 0.f;
       acc += (double)meas[r] * (double)meas[r];
     }
   }
-  s[t] = acc;
+  block_sum_store(acc, lsum + blockIdx.x);
+}
+
+__global__ __launch_bounds__(LOSS_T) void k_loss_total(const double* __restrict__ lsum, int nb,
+                                                        int64_t R, double* __restrict__ loss) {
+  __shared__ double s[LOSS_T];
+  const int t = threadIdx.x;
+  s[t] = t < nb ? lsum[t] : 0.0;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = LOSS_T / 2; o > 0; o >>= 1) {
     if (t < o) s[t] += s[t + o];
     __syncthreads();
   }
@@ -391,15 +467,23 @@ hipError_t launch_pack(int prec, const PackArgs& a, const float* P, void* Wpk, v
                            : pack_impl<PREC_F32>(a, P, Wpk, WTpk, bias, wo, st);
 }
 
+int64_t scan_blocks(int64_t n_rec) { return (n_rec + SCAN_SEG - 1) / SCAN_SEG; }
+
 hipError_t launch_rays(const GeomDev& g, const int64_t* idx, int64_t R, RayRec* rays, int32_t* nray,
                        int32_t* n_out, int64_t* off, int tile, int64_t n_tiles_max, int32_t* tr0,
-                       hipStream_t st) {
+                       int64_t* scan_ws, hipStream_t st, int pad_n) {
   const int bs = 256;
   const int64_t n_rec = R * g.sub * g.sub;  // ray records
+  const int64_t nb = scan_blocks(n_rec);
   if (R > 0)
     hipLaunchKernelGGL(k_rays, dim3((unsigned)((R + bs - 1) / bs)), dim3(bs), 0, st, g, idx, R, rays,
-                       nray, n_out);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, nray, n_rec, off);
+                       nray, n_out, pad_n);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_T), 0, st, nray, n_rec, scan_ws);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, scan_ws, nb, off + n_rec);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_T), 0, st, nray, n_rec, scan_ws,
+                       off);
   hipLaunchKernelGGL(k_tiles, dim3((unsigned)((n_tiles_max + 1 + bs - 1) / bs)), dim3(bs), 0, st,
                      off, n_rec, tile, n_tiles_max, tr0);
   return hipGetLastError();
@@ -434,6 +518,7 @@ static hipError_t mlp_dispatch(int mode, int act, const MlpArgs& a, int grid, hi
     case MODE_FUSED * 2 + 1: return mlp_launch<PREC, IN, H, MODE_FUSED, 1>(a, grid, st);
     case MODE_QUERY * 2 + 0: return mlp_launch<PREC, IN, H, MODE_QUERY, 0>(a, grid, st);
     case MODE_QUERY * 2 + 1: return mlp_launch<PREC, IN, H, MODE_QUERY, 1>(a, grid, st);
+    case MODE_GROUP * 2 + 1: return mlp_launch<PREC, IN, H, MODE_GROUP, 1>(a, grid, st);
   }
   return hipErrorInvalidValue;
 }
@@ -461,16 +546,21 @@ hipError_t launch_fixup(const RayRec* rays, const int64_t* off, int64_t R, int t
   return hipGetLastError();
 }
 
-hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* loss,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, st, proj, meas, R, g, loss);
+hipError_t launch_loss(const float* proj, const float* meas, int64_t R, float* g, double* lsum,
+                       double* loss, hipStream_t st) {
+  const int nb = loss_blocks(R);
+  hipLaunchKernelGGL(k_loss, dim3(nb), dim3(LOSS_T), 0, st, proj, meas, R, g, lsum);
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(LOSS_T), 0, st, lsum, nb, R, loss);
   return hipGetLastError();
 }
 
 hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, const double* lpart,
-                             int64_t n_lpart, float* proj, double* loss, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss_fused, dim3(1), dim3(1024), 0, st, rays, meas, R, lpart, n_lpart, proj,
-                     loss);
+                             int64_t n_lpart, float* proj, double* lsum, double* loss,
+                             int64_t n_div, hipStream_t st) {
+  const int nb = loss_blocks(R > n_lpart ? R : n_lpart);
+  hipLaunchKernelGGL(k_loss_fused, dim3(nb), dim3(LOSS_T), 0, st, rays, meas, R, lpart, n_lpart,
+                     proj, lsum);
+  hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(LOSS_T), 0, st, lsum, nb, n_div, loss);
   return hipGetLastError();
 }
 

@@ -442,6 +442,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   __shared__ __align__(16) char sW1[PANEL_BYTES];
   __shared__ float4 sB[C];
   __shared__ float sval[TILE];
+  __shared__ float scomp[TILE];  // rounding errors of the segmented scan (TwoSum)
   __shared__ int32_t srid[TILE];
   __shared__ float sg[TILE];  // fused mode: upstream gradient of the tile's rays
   __shared__ float swgt[TILE];  // query mode: weight mu0 l / n of each point's ray
@@ -458,20 +459,29 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   __shared__ uint32_t smsk[WAVES_PER_WG][MSK_LAYERS][MSK_PER_LAYER][64];
 
   constexpr bool QUERY = MODE == MODE_QUERY;
+  constexpr bool GROUP = MODE == MODE_GROUP;
+  static_assert(!GROUP || ACT == 1, "the group mode reads the activation derivatives from the stash");
+  // group mode: per-wave sums of wgt h_L over the group's tiles, each ray's
+  // (sum, Kahan compensation) and the group's upstream gradient
+  __shared__ float sU[GROUP ? WAVES_PER_WG : 1][H + 1];
+  __shared__ float sray_s[GROUP ? 64 : 1];
+  __shared__ float sray_c[GROUP ? 64 : 1];
+  __shared__ float sgp;
   const int64_t P = QUERY ? 0 : a.off[a.R];
   const int64_t n_tiles = QUERY ? a.n_qtiles : (P + TILE - 1) / TILE;
   const int64_t t_end = QUERY ? n_tiles : (a.tile_end < n_tiles ? a.tile_end : n_tiles);
   const float bo = a.params[a.bo_off];
   const int L = a.L;
-  constexpr bool FWD_PART = MODE == MODE_FWD || MODE == MODE_FUSED || MODE == MODE_QUERY;
-  constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED;
+  constexpr bool FWD_PART = MODE != MODE_BWD;
+  constexpr bool BWD_PART = MODE == MODE_BWD || MODE == MODE_FUSED || MODE == MODE_GROUP;
   // the adjoint needs the ReLU masks (or the Swish derivatives) of the
   // forward layers
   constexpr int FWD_EPI = ACT == 1 ? (BWD_PART ? EPI_SWISH_D : EPI_SWISH)
                                    : (BWD_PART ? EPI_RELU_MASK : EPI_RELU);
   constexpr int ADJ_EPI = ACT == 1 ? EPI_DERIV : EPI_MASK;
   double lossacc = 0.0;
-  const float g_scale = 2.0f / (float)a.R;
+  // dL/dpbar = g_scale (pbar - p), g_scale = 2 / (number of projections)
+  const float g_scale = 2.0f / (float)(GROUP ? a.n_proj : a.R);
   const __amdgpu_buffer_rsrc_t rW = buffer_rsrc(a.Wpk, a.wpk_bytes);
   const __amdgpu_buffer_rsrc_t rWT = buffer_rsrc(a.WTpk, a.wtpk_bytes);
   const __amdgpu_buffer_rsrc_t rB = buffer_rsrc(a.bias, (int64_t)L * H * sizeof(float));
@@ -480,8 +490,12 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   auto WTl = [&](int l) { return WSrc{rWT, (int)(a.wtpk_off[l] * ES)}; };
   const WSrc none{rW, -1};
 
-  const int64_t t0 = (QUERY ? 0 : a.tile_begin) + blockIdx.x;
-  if (t0 < t_end) dma_panel<WAVES_PER_WG>(Wl(0), sW0, PB_IN, w, lane);
+  // work units: tiles, or groups of a.group_tiles tiles (the chunk bounds are
+  // multiples of the group)
+  const int64_t u_begin = QUERY ? 0 : (GROUP ? a.tile_begin / a.group_tiles : a.tile_begin);
+  const int64_t u_end = GROUP ? t_end / a.group_tiles : t_end;
+  const int64_t u0 = u_begin + blockIdx.x;
+  if (u0 < u_end) dma_panel<WAVES_PER_WG>(Wl(0), sW0, PB_IN, w, lane);
   for (int k = threadIdx.x; k < C; k += blockDim.x) sB[k] = a.Bmat[k];
   for (int k = threadIdx.x; k < H; k += blockDim.x) {
     sBias0[k] = a.bias[k];
@@ -489,310 +503,249 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   }
   if (MODE != MODE_FWD)
     for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sdwo[0][0])[k] = 0.f;
+  if (GROUP)
+    for (int k = threadIdx.x; k < WAVES_PER_WG * (H + 1); k += blockDim.x) (&sU[0][0])[k] = 0.f;
   __syncthreads();
 
-  for (int64_t t = t0; t < t_end; t += gridDim.x) {
-    const bool more = t + gridDim.x < t_end;
-    // a zero the compiler cannot see through: keeps the per-lane loads of B
-    // rows, biases and w_o inside the tile loop instead of hoisting (and
-    // spilling) hundreds of loop-invariant values
-    int z = 0;
-    asm volatile("" : "+v"(z));
-    int rid[NB];
-    int poff[NB];  // first point of the point's ray, relative to the tile
-    float wgt[NB];
-    chunk_t x0[NB][CI];
-    // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
-    const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
-      float rt = 0.f, rz = 0.f, ry = 0.f, rx = 0.f;
-      rid[nb] = -1;
-      poff[nb] = 0;
-      wgt[nb] = 0.f;
-      if (QUERY) {
-        const QueryTile qt = a.qtiles[t];
-        const QueryDesc q = a.qdesc[qt.slot];
-        const int tp = w * (NB * 32) + nb * 32 + pl;
-        rt = q.tn;
-        if (q.kind == 0) {
-          const int64_t pq = (int64_t)qt.tile * TILE + tp;
-          if (pq < (int64_t)q.n * q.n) {
-            const int i = (int)(pq / q.n), j = (int)(pq - (int64_t)i * q.n);
-            rz = q.zn;
-            ry = -1.f + (2.f * i + 1.f) / (float)q.n;
-            rx = -1.f + (2.f * j + 1.f) / (float)q.n;
-            rid[nb] = (int)pq;
-          }
-        } else {
-          const int S = q.samples;
-          const int64_t ray = (int64_t)qt.tile * (TILE / S) + tp / S;
-          const int j = tp % S;
-          if (ray < (int64_t)q.n * q.n) {
-            const int row = (int)(ray / q.n), col = (int)(ray - (int64_t)row * q.n);
-            const GeomDev& g = a.geom;
-            const float pu = g.pitch_u * (float)g.cols / (float)q.n;
-            const float pv = g.pitch_v * (float)g.rows / (float)q.n;
-            const float u = ((float)col - 0.5f * (float)(q.n - 1)) * pu + g.off_u;
-            const float v = ((float)row - 0.5f * (float)(q.n - 1)) * pv + g.off_v;
-            const RayRec rr = make_ray(g, u, v, q.cth, q.sth, q.tn, 0, S);
-            if (rr.n > 0) {
-              const float s = rr.s_in + ((float)j + 0.5f) * rr.dl;
-              rz = rr.pz + s * rr.dz;
-              ry = rr.py + s * rr.dy;
-              rx = rr.px + s * rr.dx;
-              rid[nb] = (int)(tp / S);
-              wgt[nb] = rr.wgt;
-            } else if (j == 0 && hf == 0) {
-              q.out[ray] = 0.f;  // the ray misses the field of view
-            }
-          }
-        }
-      } else if (p < P) {
-        int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
-        if (hi > a.R - 1) hi = a.R - 1;
-        while (lo < hi) {
-          const int64_t mid = (lo + hi + 1) >> 1;
-          if (a.off[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        const RayRec rr = a.rays[lo];
-        const int j = (int)(p - a.off[lo]);
-        // midpoint, or a uniform offset in [0, 1) drawn for (j, ray, projection)
-        float u = 0.5f;
-        if (a.jitter)
-          u = (float)(philox_word0((uint32_t)j, rr.ctr1, rr.ctr2, rr.ctr3, a.key0, a.key1) >> 8) *
-              (1.0f / 16777216.0f);
-        const float s = rr.s_in + ((float)j + u) * rr.dl;
-        rt = rr.tn;
-        rz = rr.pz + s * rr.dz;
-        ry = rr.py + s * rr.dy;
-        rx = rr.px + s * rr.dx;
-        rid[nb] = (int)lo;
-        poff[nb] = (int)(a.off[lo] - t * TILE);
-        wgt[nb] = rr.wgt;
-      }
-      if (BWD_PART && hf == 0) {
-        // the layer-1 weight gradient re-derives this point's encoding from
-        // its coordinates (16 bytes instead of 2C features); padding points
-        // store zeros, which encode to finite values
-        typedef float f4 __attribute__((ext_vector_type(4)));
-        const f4 r4 = {rt, rz, ry, rx};
-        __builtin_nontemporal_store(r4, (f4*)a.stash + a.h_base[0] + (blk0 + nb) * 32 + pl);
-      }
-#pragma unroll
-      for (int c = 0; c < CI / 2; ++c) {
-        float cv[VPC], sv[VPC];
-#pragma unroll
-        for (int e = 0; e < VPC; ++e) {
-          const float f = grff_phase(sB[z + feat(VPC * c + e, hf)], rt, rz, ry, rx);
-          sincos_rev<PREC>(f, &sv[e], &cv[e]);
-        }
-        x0[nb][c] = T::from_f32(cv);
-        x0[nb][c + CI / 2] = T::from_f32(sv);
-        // materialise the encoded chunk here: otherwise the arithmetic sinks
-        // past the first panel barrier to its use, and the B rows of every
-        // chunk stay live across it
-        pin(x0[nb][c]);
-        pin(x0[nb][c + CI / 2]);
-      }
-    }
-    uint32_t* msk_w = &smsk[w][0][0][0];
+  if constexpr (GROUP) {
+    // ---- stash addresses of a tile: its first 32-point block for this wave
+    auto blk_of = [&](int64_t t) -> int64_t { return (t - a.tile_begin) * (TILE / 32) + w * NB; };
     // Swish derivatives of layer l's outputs, in the layout of the stash
-    auto astash = [&](int l) -> chunk_t* {
+    auto astash = [&](int64_t blk0, int l) -> chunk_t* {
       return (BWD_PART && ACT == 1) ? (chunk_t*)a.stash + a.a_base[l] + blk0 * (CHh * 64)
                                     : nullptr;
     };
-    auto hstash = [&](int l, int ch) -> chunk_t* {
+    auto hstash = [&](int64_t blk0, int l, int ch) -> chunk_t* {
       return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
     };
-    // what follows the last forward layer in the panel sequence
-    const WSrc after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : none);
+    auto dstash = [&](int64_t blk0, int l) {
+      return (chunk_t*)a.stash + a.d_base[l] + blk0 * (CHh * 64);
+    };
+    uint32_t* msk_w = &smsk[w][0][0][0];
     // biases of layer l+1 (none after the last layer: layer 0's stay resident)
     auto bias_next = [&](int l) -> WSrc {
       return l + 1 < L ? WSrc{rB, (l + 1) * H * (int)sizeof(float)} : none;
     };
-    const int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
-    // ---- hidden layers (Appendix B item 3)
-    chunk_t y[NB][CHh];
-    {
-      uint32_t mk[MSK_PER_LAYER];
-      const WSrc nx = L > 1 ? Wl(1) : after_fwd;
-      const int nxb = L > 1 ? PB_H : after_fwd_bytes;
-      layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
-                                           mk, nullptr, sW0, sW1, lane, w, z, astash(0));
-      if (BWD_PART && ACT == 0 && L > 1)
-#pragma unroll
-        for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
-    }
-    // hidden layers 2..L, two per iteration with the roles of y and z swapped
-    // so that no activation array is copied between layers
-    // sb: this layer's biases, sbn: where the next layer's go
-    auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh],
-                      const float* sb, float* sbn) {
-      uint32_t mk[MSK_PER_LAYER];
-      const WSrc nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
-      const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
-      // stores the previous layer issued after its last DMA: its last panel's
-      // share (layer 0 stores none: its input is re-derived from coordinates)
-      constexpr int VM_1 = 0;
-      constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
-      if (VM_1 != VM_H && l == 1)
-        layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
-                                                 hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
-      else
-        layer<PREC, CHh, H, FWD_EPI, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
-                                                 hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
-      if (BWD_PART && ACT == 0 && l < L - 1)
-#pragma unroll
-        for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
-    };
-    for (int l = 1; l < L; l += 2) {
-      chunk_t t2[NB][CHh];
-      hidden(l, y, t2, sBiasOdd, sBiasEven);
-      if (l + 1 < L) {
-        hidden(l + 1, t2, y, sBiasEven, sBiasOdd);
-      } else {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int c = 0; c < CHh; ++c) y[nb][c] = t2[nb][c];
-      }
-    }
-    // ---- output unit (Appendix B item 4) with the configured output map
-    float zo[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
-    const float* wop = sWo + z + hf * (H / 2);
-#pragma unroll
-    for (int c = 0; c < CHh; ++c) {
-#pragma unroll
-      for (int e = 0; e < VPC; ++e) {
-        const float wv = wop[VPC * c + e];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) zo[nb] += wv * T::get(y[nb][c], e);
-      }
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) zo[nb] += __shfl_xor(zo[nb], 32) + bo;
 
-    if (FWD_PART) {
-      // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
-      const QueryDesc* qd = QUERY ? &a.qdesc[a.qtiles[t].slot] : nullptr;
-      const bool slice = QUERY && qd->kind == 0;
+    // ---- forward of tile t: coordinates, Fourier features, hidden layers and
+    // the output unit.  Leaves each point's ray (rid; poff, the ray's first
+    // point relative to the tile; its weight), h_L and the output pre-activation.
+    // after_fwd: the first weight panel that follows the last forward layer.
+    auto forward = [&](int64_t t, int z, WSrc after_fwd, int after_fwd_bytes, int (&rid)[NB],
+                       int (&poff)[NB], float (&wgt)[NB], chunk_t (&y)[NB][CHh], float (&zo)[NB]) {
+      const int64_t blk0 = blk_of(t);
+      chunk_t x0[NB][CI];
+      // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const float z = zo[nb];
-        const float M = a.out_act ? fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) : z;
-        if (hf == 0) {
+        const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
+        float rt = 0.f, rz = 0.f, ry = 0.f, rx = 0.f;
+        rid[nb] = -1;
+        poff[nb] = 0;
+        wgt[nb] = 0.f;
+        if (QUERY) {
+          const QueryTile qt = a.qtiles[t];
+          const QueryDesc q = a.qdesc[qt.slot];
           const int tp = w * (NB * 32) + nb * 32 + pl;
-          if (slice) {
-            if (rid[nb] >= 0) qd->out[rid[nb]] = a.geom.mu0 * M;  // mu0 M: attenuation
-            srid[tp] = -1;
+          rt = q.tn;
+          if (q.kind == 0) {
+            const int64_t pq = (int64_t)qt.tile * TILE + tp;
+            if (pq < (int64_t)q.n * q.n) {
+              const int i = (int)(pq / q.n), j = (int)(pq - (int64_t)i * q.n);
+              rz = q.zn;
+              ry = -1.f + (2.f * i + 1.f) / (float)q.n;
+              rx = -1.f + (2.f * j + 1.f) / (float)q.n;
+              rid[nb] = (int)pq;
+            }
           } else {
-            sval[tp] = rid[nb] >= 0 ? M : 0.f;
-            srid[tp] = rid[nb];
-            if (QUERY) swgt[tp] = wgt[nb];
-          }
-        }
-      }
-      __syncthreads();
-      const int tp = threadIdx.x;
-      for (int o = 1; o < TILE; o <<= 1) {
-        float add = 0.f;
-        if (tp < TILE && tp >= o && srid[tp - o] == srid[tp]) add = sval[tp - o];
-        __syncthreads();
-        if (tp < TILE) sval[tp] += add;
-        __syncthreads();
-      }
-      if (tp < TILE) {
-        const int r = srid[tp];
-        if (r >= 0 && (tp == TILE - 1 || srid[tp + 1] != r)) {
-          const int64_t o0 = QUERY ? 0 : a.off[r];
-          const int64_t o1 = QUERY ? 0 : a.off[r + 1];
-          const int64_t tb = t * TILE;
-          const float sum = sval[tp];
-          if (QUERY) {
-            // whole rays per tile: ray rid of this tile
-            const QueryTile qt = a.qtiles[t];
-            const int64_t ray = (int64_t)qt.tile * (TILE / qd->samples) + r;
-            qd->out[ray] = __fmul_rn(swgt[tp], sum);
-          } else if (MODE == MODE_FUSED) {
-            // whole ray in this tile: prediction, residual, upstream gradient
-            // rounded product (no contraction into the residual), as in the
-            // forward kernel, so both passes produce the same residuals
-            const float pbar = __fmul_rn(a.rays[r].wgt, sum);
-            a.proj[r] = pbar;
-            const float e = pbar - a.meas[r];
-            lossacc += (double)e * (double)e;
-            sg[o0 - tb] = g_scale * e;
-          } else if (o0 < tb) {
-            a.part[2 * t + 0] = sum;
-          } else if (o1 > tb + TILE) {
-            a.part[2 * t + 1] = sum;
-          } else {
-            a.proj[r] = __fmul_rn(a.rays[r].wgt, sum);
-          }
-        }
-      }
-      __syncthreads();
-    }
-    if (BWD_PART) {
-      // ---- adjoint (Eq. (8)): dL/dM = g_r mu0 l_r / n_r, through the output map
-      float dob[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const float z = zo[nb];
-        const float dMdz = a.out_act ? 1.f / (1.f + expf(-z)) : 1.f;
-        float gr = 0.f;
-        if (rid[nb] >= 0) gr = MODE == MODE_FUSED ? sg[poff[nb]] : a.gup[rid[nb]];
-        dob[nb] = gr * wgt[nb] * dMdz;
-      }
-      // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
-      // Halving butterfly over the 32 lanes of each half, in two passes over
-      // the slots: after 5 steps lane pl holds the sums of KF consecutive slots.
-      {
-        constexpr int K = 32;  // slots per pass (the butterfly needs a multiple of 32)
-#pragma unroll
-        for (int pass = 0; pass < (H / 2) / K; ++pass) {
-          float v[K];
-#pragma unroll
-          for (int i = 0; i < K; ++i) {
-            const int rho = pass * K + i;
-            float s = 0.f;
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][rho / VPC], rho % VPC);
-            v[i] = s;
-          }
-#pragma unroll
-          for (int st = 0; st < 5; ++st) {
-            const int o = 16 >> st;
-            const int half = K >> (st + 1);
-            const bool up = (pl & o) != 0;
-#pragma unroll
-            for (int i = 0; i < half; ++i) {
-              const float send = up ? v[i] : v[i + half];
-              const float keep = up ? v[i + half] : v[i];
-              v[i] = keep + __shfl_xor(send, o);
+            const int S = q.samples;
+            const int64_t ray = (int64_t)qt.tile * (TILE / S) + tp / S;
+            const int j = tp % S;
+            if (ray < (int64_t)q.n * q.n) {
+              const int row = (int)(ray / q.n), col = (int)(ray - (int64_t)row * q.n);
+              const GeomDev& g = a.geom;
+              const float pu = g.pitch_u * (float)g.cols / (float)q.n;
+              const float pv = g.pitch_v * (float)g.rows / (float)q.n;
+              const float u = ((float)col - 0.5f * (float)(q.n - 1)) * pu + g.off_u;
+              const float v = ((float)row - 0.5f * (float)(q.n - 1)) * pv + g.off_v;
+              const RayRec rr = make_ray(g, u, v, q.cth, q.sth, q.tn, 0, S);
+              if (rr.n > 0) {
+                const float s = rr.s_in + ((float)j + 0.5f) * rr.dl;
+                rz = rr.pz + s * rr.dz;
+                ry = rr.py + s * rr.dy;
+                rx = rr.px + s * rr.dx;
+                rid[nb] = (int)(tp / S);
+                wgt[nb] = rr.wgt;
+              } else if (j == 0 && hf == 0) {
+                q.out[ray] = 0.f;  // the ray misses the field of view
+              }
             }
           }
-          constexpr int KF = K / 32;
-#pragma unroll
-          for (int i = 0; i < KF; ++i) sdwo[w][feat(pass * K + KF * pl + i, hf)] += v[i];
+        } else if (p < P) {
+          int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
+          if (hi > a.R - 1) hi = a.R - 1;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.off[mid] <= p) lo = mid; else hi = mid - 1;
+          }
+          const RayRec rr = a.rays[lo];
+          const int j = (int)(p - a.off[lo]);
+          // midpoint, or a uniform offset in [0, 1) drawn for (j, ray, projection)
+          float u = 0.5f;
+          if (a.jitter)
+            u = (float)(philox_word0((uint32_t)j, rr.ctr1, rr.ctr2, rr.ctr3, a.key0, a.key1) >> 8) *
+                (1.0f / 16777216.0f);
+          const float s = rr.s_in + ((float)j + u) * rr.dl;
+          rt = rr.tn;
+          rz = rr.pz + s * rr.dz;
+          ry = rr.py + s * rr.dy;
+          rx = rr.px + s * rr.dx;
+          rid[nb] = (int)lo;
+          poff[nb] = (int)(a.off[lo] - t * TILE);
+          wgt[nb] = rr.wgt;
         }
-        float sb = 0.f;
+        if (BWD_PART && hf == 0) {
+          // the layer-1 weight gradient re-derives this point's encoding from
+          // its coordinates (16 bytes instead of 2C features); padding points
+          // store zeros, which encode to finite values
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          const f4 r4 = {rt, rz, ry, rx};
+          __builtin_nontemporal_store(r4, (f4*)a.stash + a.h_base[0] + (blk0 + nb) * 32 + pl);
+        }
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) sb += dob[nb];
+        for (int c = 0; c < CI / 2; ++c) {
+          float cv[VPC], sv[VPC];
 #pragma unroll
-        for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
-        if (lane == 0) sdwo[w][H] += sb;
+          for (int e = 0; e < VPC; ++e) {
+            const float f = grff_phase(sB[z + feat(VPC * c + e, hf)], rt, rz, ry, rx);
+            sincos_rev<PREC>(f, &sv[e], &cv[e]);
+          }
+          x0[nb][c] = T::from_f32(cv);
+          x0[nb][c + CI / 2] = T::from_f32(sv);
+          // materialise the encoded chunk here: otherwise the arithmetic sinks
+          // past the first panel barrier to its use, and the B rows of every
+          // chunk stay live across it
+          pin(x0[nb][c]);
+          pin(x0[nb][c + CI / 2]);
+        }
       }
+      // ---- hidden layers (Appendix B item 3)
+      {
+        uint32_t mk[MSK_PER_LAYER];
+        const WSrc nx = L > 1 ? Wl(1) : after_fwd;
+        const int nxb = L > 1 ? PB_H : after_fwd_bytes;
+        layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
+                                             mk, nullptr, sW0, sW1, lane, w, z, astash(blk0, 0));
+        if (BWD_PART && ACT == 0 && L > 1)
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+      }
+      // hidden layers 2..L, two per iteration with the roles of y and z swapped
+      // so that no activation array is copied between layers
+      // sb: this layer's biases, sbn: where the next layer's go
+      auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh],
+                        const float* sb, float* sbn) {
+        uint32_t mk[MSK_PER_LAYER];
+        const WSrc nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
+        const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
+        // stores the previous layer issued after its last DMA: its last panel's
+        // share (layer 0 stores none: its input is re-derived from coordinates)
+        constexpr int VM_1 = 0;
+        constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
+        if (VM_1 != VM_H && l == 1)
+          layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                   hstash(blk0, l, CHh), sW0, sW1, lane, w, z, astash(blk0, l));
+        else
+          layer<PREC, CHh, H, FWD_EPI, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                   hstash(blk0, l, CHh), sW0, sW1, lane, w, z, astash(blk0, l));
+        if (BWD_PART && ACT == 0 && l < L - 1)
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+      };
+      for (int l = 1; l < L; l += 2) {
+        chunk_t t2[NB][CHh];
+        hidden(l, y, t2, sBiasOdd, sBiasEven);
+        if (l + 1 < L) {
+          hidden(l + 1, t2, y, sBiasEven, sBiasOdd);
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c) y[nb][c] = t2[nb][c];
+        }
+      }
+      // ---- output unit (Appendix B item 4) with the configured output map
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
+      const float* wop = sWo + z + hf * (H / 2);
+#pragma unroll
+      for (int c = 0; c < CHh; ++c) {
+#pragma unroll
+        for (int e = 0; e < VPC; ++e) {
+          const float wv = wop[VPC * c + e];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) zo[nb] += wv * T::get(y[nb][c], e);
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) zo[nb] += __shfl_xor(zo[nb], 32) + bo;
+    };
+
+    // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
+    // Halving butterfly over the 32 lanes of each half, in two passes over
+    // the slots: after 5 steps lane pl holds the sums of KF consecutive slots.
+    // (dst: this wave's row of an LDS array; dst[H] receives db_o)
+    auto dwo_acc = [&](const float (&dob)[NB], const chunk_t (&y)[NB][CHh], float* dst) {
+      constexpr int K = 32;  // slots per pass (the butterfly needs a multiple of 32)
+#pragma unroll
+      for (int pass = 0; pass < (H / 2) / K; ++pass) {
+        float v[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const int rho = pass * K + i;
+          float s = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][rho / VPC], rho % VPC);
+          v[i] = s;
+        }
+#pragma unroll
+        for (int st = 0; st < 5; ++st) {
+          const int o = 16 >> st;
+          const int half = K >> (st + 1);
+          const bool up = (pl & o) != 0;
+#pragma unroll
+          for (int i = 0; i < half; ++i) {
+            const float send = up ? v[i] : v[i + half];
+            const float keep = up ? v[i + half] : v[i];
+            v[i] = keep + __shfl_xor(send, o);
+          }
+        }
+        constexpr int KF = K / 32;
+#pragma unroll
+        for (int i = 0; i < KF; ++i) dst[feat(pass * K + KF * pl + i, hf)] += v[i];
+      }
+      float sb = 0.f;
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) sb += dob[nb];
+#pragma unroll
+      for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
+      if (lane == 0) dst[H] += sb;
+    };
+
+    // ---- adjoint of tile t (Eq. (8)) from dL/dz_o of its points: delta_L, the
+    // delta chain through the transposed layers, the operand stash.
+    // after: the first weight panel that follows the last adjoint layer.
+    auto adjoint = [&](int64_t t, int z, const float (&dob)[NB], const chunk_t (&y)[NB][CHh],
+                       WSrc after, int after_bytes) {
+      const int64_t blk0 = blk_of(t);
+      const float* wop = sWo + z + hf * (H / 2);
       // delta_L = w_o dob . act'(z_L)
       chunk_t d[NB][CHh];
       if (ACT == 1) {
         // Swish: the last layer's derivatives, just stored by this wave
         wait_vm<0>();
-        const char* ap = (const char*)astash(L - 1) + lane_off((uint32_t)(lane * sizeof(chunk_t)));
+        const char* ap = (const char*)astash(blk0, L - 1) +
+                         lane_off((uint32_t)(lane * sizeof(chunk_t)));
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
@@ -822,13 +775,12 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
           d[nb][c] = T::from_f32(v);
         }
       }
-      auto dstash = [&](int l) { return (chunk_t*)a.stash + a.d_base[l] + blk0 * (CHh * 64); };
       if (L == 1) {
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int c = 0; c < CHh; ++c)
-            T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
+            T::store_nt(&dstash(blk0, 0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
       }
       // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
       // call stores its input delta_l for the weight gradient.  Two layers per
@@ -839,13 +791,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
 #pragma unroll
           for (int k = 0; k < MSK_PER_LAYER; ++k)
             mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
-        const WSrc nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : none);
-        const int nxb = l > 1 ? PB_H : PB_IN;
+        const WSrc nx = l > 1 ? WTl(l - 1) : after;
+        const int nxb = l > 1 ? PB_H : after_bytes;
         // entering from the forward's last layer or from the previous adjoint
         // layer: both stored their last panel's share of a width-H input
         layer<PREC, CHh, H, ADJ_EPI, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
-            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z,
-            astash(l - 1));
+            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(blk0, l), sW0, sW1, lane, w, z,
+            astash(blk0, l - 1));
       };
       for (int l = L - 1; l >= 1; l -= 2) {
         chunk_t t2[NB][CHh];
@@ -864,7 +816,565 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int c = 0; c < CHh; ++c)
-            T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
+            T::store_nt(&dstash(blk0, 0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
+      }
+    };
+
+    // Work units: tiles, or (group mode) groups of G consecutive tiles that
+    // hold one projection each.
+    const int G = GROUP ? a.group_tiles : 1;
+    for (int64_t u = u0; u < u_end; u += gridDim.x) {
+      const bool more = u + gridDim.x < u_end;
+      for (int k = 0; k < G; ++k) {
+        const int64_t t = u * G + k;
+        // a zero the compiler cannot see through: keeps the per-lane loads of B
+        // rows, biases and w_o inside the tile loop instead of hoisting (and
+        // spilling) hundreds of loop-invariant values
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        int rid[NB];
+        int poff[NB];
+        float wgt[NB];
+        chunk_t y[NB][CHh];
+        float zo[NB];
+        // what follows the last forward layer in the panel sequence: the
+        // adjoint (its last layer's transposed weights) or the next tile; in
+        // the group mode the next tile of the group until its last
+        WSrc after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : none);
+        int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
+        if (GROUP && k + 1 < G) {
+          after_fwd = Wl(0);
+          after_fwd_bytes = PB_IN;
+        }
+        forward(t, z, after_fwd, after_fwd_bytes, rid, poff, wgt, y, zo);
+        if (FWD_PART) {
+          // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
+          const QueryDesc* qd = QUERY ? &a.qdesc[a.qtiles[t].slot] : nullptr;
+          const bool slice = QUERY && qd->kind == 0;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            const float z = zo[nb];
+            const float M = a.out_act ? fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) : z;
+            if (hf == 0) {
+              const int tp = w * (NB * 32) + nb * 32 + pl;
+              if (slice) {
+                if (rid[nb] >= 0) qd->out[rid[nb]] = a.geom.mu0 * M;  // mu0 M: attenuation
+                srid[tp] = -1;
+              } else {
+                sval[tp] = rid[nb] >= 0 ? M : 0.f;
+                scomp[tp] = 0.f;
+                srid[tp] = rid[nb];
+                if (QUERY) swgt[tp] = wgt[nb];
+              }
+            }
+          }
+          __syncthreads();
+          // inclusive scan of every ray's samples in the tile, compensated: each
+          // step adds the partial o places back with TwoSum (Knuth) and carries
+          // the rounding error, so a ray's sum is s + c with the error of a few
+          // roundings whatever its number of samples and their magnitudes
+          const int tp = threadIdx.x;
+          for (int o = 1; o < TILE; o <<= 1) {
+            float add = 0.f, addc = 0.f;
+            if (tp < TILE && tp >= o && srid[tp - o] == srid[tp]) {
+              add = sval[tp - o];
+              addc = scomp[tp - o];
+            }
+            __syncthreads();
+            if (tp < TILE) {
+              const float x = sval[tp];
+              const float s = x + add;
+              const float bv = s - x;
+              const float err = (x - (s - bv)) + (add - bv);
+              sval[tp] = s;
+              scomp[tp] = (scomp[tp] + addc) + err;
+            }
+            __syncthreads();
+          }
+          if (tp < TILE) {
+            const int r = srid[tp];
+            if (r >= 0 && (tp == TILE - 1 || srid[tp + 1] != r)) {
+              const int64_t o0 = QUERY ? 0 : a.off[r];
+              const int64_t o1 = QUERY ? 0 : a.off[r + 1];
+              const int64_t tb = t * TILE;
+              const float sum = sval[tp] + scomp[tp];
+              if (GROUP) {
+                // the tile lies inside one ray: its sum is added to the ray's,
+                // Kahan in tile order as k_fixup adds a ray's tile partials
+                const int kr = k / a.tiles_per_ray;
+                if (k % a.tiles_per_ray == 0) {
+                  sray_s[kr] = sum;
+                  sray_c[kr] = 0.f;
+                } else {
+                  const float yv = sum - sray_c[kr];
+                  const float tt = sray_s[kr] + yv;
+                  sray_c[kr] = (tt - sray_s[kr]) - yv;
+                  sray_s[kr] = tt;
+                }
+              } else if (QUERY) {
+                // whole rays per tile: ray rid of this tile
+                const QueryTile qt = a.qtiles[t];
+                const int64_t ray = (int64_t)qt.tile * (TILE / qd->samples) + r;
+                qd->out[ray] = __fmul_rn(swgt[tp], sum);
+              } else if (MODE == MODE_FUSED) {
+                // whole ray in this tile: prediction, residual, upstream gradient
+                // rounded product (no contraction into the residual), as in the
+                // forward kernel, so both passes produce the same residuals
+                const float pbar = __fmul_rn(a.rays[r].wgt, sum);
+                a.proj[r] = pbar;
+                const float e = pbar - a.meas[r];
+                lossacc += (double)e * (double)e;
+                sg[o0 - tb] = g_scale * e;
+              } else if (o0 < tb) {
+                a.part[2 * t + 0] = sum;
+              } else if (o1 > tb + TILE) {
+                a.part[2 * t + 1] = sum;
+              } else {
+                a.proj[r] = __fmul_rn(a.rays[r].wgt, sum);
+              }
+            }
+          }
+          __syncthreads();
+        }
+        if (GROUP) {
+          // the group's dw_o is g_proj sum_k wgt_k sum_{p in tile k} h_L,p (a
+          // linear output: dM/dz = 1); the weighted sum waits for g_proj
+          dwo_acc(wgt, y, &sU[w][0]);
+        }
+      }
+      if constexpr (GROUP) {
+        // ---- the group's projection (Eq. (1), App. A): its rays' weighted sums
+        // added in FP64 and rounded once, as k_bundle adds them; the residual,
+        // its loss term and the upstream gradient 2 (pbar - p) / R (Eq. (5))
+        if (threadIdx.x == 0) {
+          const int64_t r = u;
+          double acc = 0.0;
+          bool bad = false;
+          for (int kr = 0; kr < a.d2; ++kr) {
+            const int64_t q = r * a.d2 + kr;
+            bad = bad || (a.rays[q].flags & 1) != 0;
+            acc += (double)__fmul_rn(a.rays[q].wgt, sray_s[kr]);
+          }
+          const float pbar = bad ? __builtin_nanf("") : (float)acc;
+          a.proj[r] = pbar;
+          const float e = pbar - a.meas[r];
+          lossacc += (double)e * (double)e;
+          sgp = g_scale * e;
+        }
+        __syncthreads();
+        const float gp = sgp;
+        for (int f = lane; f <= H; f += 64) {
+          sdwo[w][f] += gp * sU[w][f];
+          sU[w][f] = 0.f;
+        }
+        // ---- the adjoint of the group's tiles: every point of tile t belongs
+        // to ray record t / m (m tiles per ray; a ray that misses the field of
+        // view is padded to n points of weight 0)
+        for (int k = 0; k < G; ++k) {
+          const int64_t t = u * G + k;
+          int z = 0;
+          asm volatile("" : "+v"(z));
+          const float wt = a.rays[t / a.tiles_per_ray].wgt;
+          float dob[NB];
+          chunk_t y[NB][CHh];  // h_L: the Swish adjoint does not read it
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) dob[nb] = gp * wt;
+          const bool last = k + 1 == G;
+          adjoint(t, z, dob, y, last ? (more ? Wl(0) : none) : WTl(L - 1), last ? PB_IN : PB_H);
+        }
+      }
+    }
+  } else {
+    for (int64_t t = u0; t < t_end; t += gridDim.x) {
+      const bool more = t + gridDim.x < t_end;
+      // a zero the compiler cannot see through: keeps the per-lane loads of B
+      // rows, biases and w_o inside the tile loop instead of hoisting (and
+      // spilling) hundreds of loop-invariant values
+      int z = 0;
+      asm volatile("" : "+v"(z));
+      int rid[NB];
+      int poff[NB];  // first point of the point's ray, relative to the tile
+      float wgt[NB];
+      chunk_t x0[NB][CI];
+      // ---- coordinates and Fourier features (Appendix A, Appendix B items 1-2)
+      const int64_t blk0 = (t - a.tile_begin) * (TILE / 32) + w * NB;  // stash block of nb = 0
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t p = t * TILE + w * (NB * 32) + nb * 32 + pl;
+        float rt = 0.f, rz = 0.f, ry = 0.f, rx = 0.f;
+        rid[nb] = -1;
+        poff[nb] = 0;
+        wgt[nb] = 0.f;
+        if (QUERY) {
+          const QueryTile qt = a.qtiles[t];
+          const QueryDesc q = a.qdesc[qt.slot];
+          const int tp = w * (NB * 32) + nb * 32 + pl;
+          rt = q.tn;
+          if (q.kind == 0) {
+            const int64_t pq = (int64_t)qt.tile * TILE + tp;
+            if (pq < (int64_t)q.n * q.n) {
+              const int i = (int)(pq / q.n), j = (int)(pq - (int64_t)i * q.n);
+              rz = q.zn;
+              ry = -1.f + (2.f * i + 1.f) / (float)q.n;
+              rx = -1.f + (2.f * j + 1.f) / (float)q.n;
+              rid[nb] = (int)pq;
+            }
+          } else {
+            const int S = q.samples;
+            const int64_t ray = (int64_t)qt.tile * (TILE / S) + tp / S;
+            const int j = tp % S;
+            if (ray < (int64_t)q.n * q.n) {
+              const int row = (int)(ray / q.n), col = (int)(ray - (int64_t)row * q.n);
+              const GeomDev& g = a.geom;
+              const float pu = g.pitch_u * (float)g.cols / (float)q.n;
+              const float pv = g.pitch_v * (float)g.rows / (float)q.n;
+              const float u = ((float)col - 0.5f * (float)(q.n - 1)) * pu + g.off_u;
+              const float v = ((float)row - 0.5f * (float)(q.n - 1)) * pv + g.off_v;
+              const RayRec rr = make_ray(g, u, v, q.cth, q.sth, q.tn, 0, S);
+              if (rr.n > 0) {
+                const float s = rr.s_in + ((float)j + 0.5f) * rr.dl;
+                rz = rr.pz + s * rr.dz;
+                ry = rr.py + s * rr.dy;
+                rx = rr.px + s * rr.dx;
+                rid[nb] = (int)(tp / S);
+                wgt[nb] = rr.wgt;
+              } else if (j == 0 && hf == 0) {
+                q.out[ray] = 0.f;  // the ray misses the field of view
+              }
+            }
+          }
+        } else if (p < P) {
+          int64_t lo = a.tile_ray0[t], hi = a.tile_ray0[t + 1];
+          if (hi > a.R - 1) hi = a.R - 1;
+          while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.off[mid] <= p) lo = mid; else hi = mid - 1;
+          }
+          const RayRec rr = a.rays[lo];
+          const int j = (int)(p - a.off[lo]);
+          // midpoint, or a uniform offset in [0, 1) drawn for (j, ray, projection)
+          float u = 0.5f;
+          if (a.jitter)
+            u = (float)(philox_word0((uint32_t)j, rr.ctr1, rr.ctr2, rr.ctr3, a.key0, a.key1) >> 8) *
+                (1.0f / 16777216.0f);
+          const float s = rr.s_in + ((float)j + u) * rr.dl;
+          rt = rr.tn;
+          rz = rr.pz + s * rr.dz;
+          ry = rr.py + s * rr.dy;
+          rx = rr.px + s * rr.dx;
+          rid[nb] = (int)lo;
+          poff[nb] = (int)(a.off[lo] - t * TILE);
+          wgt[nb] = rr.wgt;
+        }
+        if (BWD_PART && hf == 0) {
+          // the layer-1 weight gradient re-derives this point's encoding from
+          // its coordinates (16 bytes instead of 2C features); padding points
+          // store zeros, which encode to finite values
+          typedef float f4 __attribute__((ext_vector_type(4)));
+          const f4 r4 = {rt, rz, ry, rx};
+          __builtin_nontemporal_store(r4, (f4*)a.stash + a.h_base[0] + (blk0 + nb) * 32 + pl);
+        }
+#pragma unroll
+        for (int c = 0; c < CI / 2; ++c) {
+          float cv[VPC], sv[VPC];
+#pragma unroll
+          for (int e = 0; e < VPC; ++e) {
+            const float f = grff_phase(sB[z + feat(VPC * c + e, hf)], rt, rz, ry, rx);
+            sincos_rev<PREC>(f, &sv[e], &cv[e]);
+          }
+          x0[nb][c] = T::from_f32(cv);
+          x0[nb][c + CI / 2] = T::from_f32(sv);
+          // materialise the encoded chunk here: otherwise the arithmetic sinks
+          // past the first panel barrier to its use, and the B rows of every
+          // chunk stay live across it
+          pin(x0[nb][c]);
+          pin(x0[nb][c + CI / 2]);
+        }
+      }
+      uint32_t* msk_w = &smsk[w][0][0][0];
+      // Swish derivatives of layer l's outputs, in the layout of the stash
+      auto astash = [&](int l) -> chunk_t* {
+        return (BWD_PART && ACT == 1) ? (chunk_t*)a.stash + a.a_base[l] + blk0 * (CHh * 64)
+                                      : nullptr;
+      };
+      auto hstash = [&](int l, int ch) -> chunk_t* {
+        return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
+      };
+      // what follows the last forward layer in the panel sequence
+      const WSrc after_fwd = (BWD_PART && L > 1) ? WTl(L - 1) : (more ? Wl(0) : none);
+      // biases of layer l+1 (none after the last layer: layer 0's stay resident)
+      auto bias_next = [&](int l) -> WSrc {
+        return l + 1 < L ? WSrc{rB, (l + 1) * H * (int)sizeof(float)} : none;
+      };
+      const int after_fwd_bytes = (BWD_PART && L > 1) ? PB_H : PB_IN;
+      // ---- hidden layers (Appendix B item 3)
+      chunk_t y[NB][CHh];
+      {
+        uint32_t mk[MSK_PER_LAYER];
+        const WSrc nx = L > 1 ? Wl(1) : after_fwd;
+        const int nxb = L > 1 ? PB_H : after_fwd_bytes;
+        layer<PREC, CI, H, FWD_EPI, 0>(x0, y, Wl(0), nx, nxb, sBias0, bias_next(0), sBiasOdd,
+                                             mk, nullptr, sW0, sW1, lane, w, z, astash(0));
+        if (BWD_PART && ACT == 0 && L > 1)
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(0 * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+      }
+      // hidden layers 2..L, two per iteration with the roles of y and z swapped
+      // so that no activation array is copied between layers
+      // sb: this layer's biases, sbn: where the next layer's go
+      auto hidden = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh],
+                        const float* sb, float* sbn) {
+        uint32_t mk[MSK_PER_LAYER];
+        const WSrc nx = (l + 1 < L) ? Wl(l + 1) : after_fwd;
+        const int nxb = (l + 1 < L) ? PB_H : after_fwd_bytes;
+        // stores the previous layer issued after its last DMA: its last panel's
+        // share (layer 0 stores none: its input is re-derived from coordinates)
+        constexpr int VM_1 = 0;
+        constexpr int VM_H = BWD_PART ? NB * (CHh / (H / 32 / panel_obs<CHh, H>())) : 0;
+        if (VM_1 != VM_H && l == 1)
+          layer<PREC, CHh, H, FWD_EPI, VM_1>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                   hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
+        else
+          layer<PREC, CHh, H, FWD_EPI, VM_H>(in, out, Wl(l), nx, nxb, sb, bias_next(l), sbn, mk,
+                                                   hstash(l, CHh), sW0, sW1, lane, w, z, astash(l));
+        if (BWD_PART && ACT == 0 && l < L - 1)
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+      };
+      for (int l = 1; l < L; l += 2) {
+        chunk_t t2[NB][CHh];
+        hidden(l, y, t2, sBiasOdd, sBiasEven);
+        if (l + 1 < L) {
+          hidden(l + 1, t2, y, sBiasEven, sBiasOdd);
+        } else {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c) y[nb][c] = t2[nb][c];
+        }
+      }
+      // ---- output unit (Appendix B item 4) with the configured output map
+      float zo[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) zo[nb] = 0.f;
+      const float* wop = sWo + z + hf * (H / 2);
+#pragma unroll
+      for (int c = 0; c < CHh; ++c) {
+#pragma unroll
+        for (int e = 0; e < VPC; ++e) {
+          const float wv = wop[VPC * c + e];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) zo[nb] += wv * T::get(y[nb][c], e);
+        }
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) zo[nb] += __shfl_xor(zo[nb], 32) + bo;
+
+      if (FWD_PART) {
+        // ---- segmented ray-sum (Eq. (1)): scan within the tile, partials out
+        const QueryDesc* qd = QUERY ? &a.qdesc[a.qtiles[t].slot] : nullptr;
+        const bool slice = QUERY && qd->kind == 0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float z = zo[nb];
+          const float M = a.out_act ? fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) : z;
+          if (hf == 0) {
+            const int tp = w * (NB * 32) + nb * 32 + pl;
+            if (slice) {
+              if (rid[nb] >= 0) qd->out[rid[nb]] = a.geom.mu0 * M;  // mu0 M: attenuation
+              srid[tp] = -1;
+            } else {
+              sval[tp] = rid[nb] >= 0 ? M : 0.f;
+              scomp[tp] = 0.f;
+              srid[tp] = rid[nb];
+              if (QUERY) swgt[tp] = wgt[nb];
+            }
+          }
+        }
+        __syncthreads();
+        // inclusive scan of every ray's samples in the tile, compensated: each
+        // step adds the partial o places back with TwoSum (Knuth) and carries
+        // the rounding error, so a ray's sum is s + c with the error of a few
+        // roundings whatever its number of samples and their magnitudes
+        const int tp = threadIdx.x;
+        for (int o = 1; o < TILE; o <<= 1) {
+          float add = 0.f, addc = 0.f;
+          if (tp < TILE && tp >= o && srid[tp - o] == srid[tp]) {
+            add = sval[tp - o];
+            addc = scomp[tp - o];
+          }
+          __syncthreads();
+          if (tp < TILE) {
+            const float x = sval[tp];
+            const float s = x + add;
+            const float bv = s - x;
+            const float err = (x - (s - bv)) + (add - bv);
+            sval[tp] = s;
+            scomp[tp] = (scomp[tp] + addc) + err;
+          }
+          __syncthreads();
+        }
+        if (tp < TILE) {
+          const int r = srid[tp];
+          if (r >= 0 && (tp == TILE - 1 || srid[tp + 1] != r)) {
+            const int64_t o0 = QUERY ? 0 : a.off[r];
+            const int64_t o1 = QUERY ? 0 : a.off[r + 1];
+            const int64_t tb = t * TILE;
+            const float sum = sval[tp] + scomp[tp];
+            if (QUERY) {
+              // whole rays per tile: ray rid of this tile
+              const QueryTile qt = a.qtiles[t];
+              const int64_t ray = (int64_t)qt.tile * (TILE / qd->samples) + r;
+              qd->out[ray] = __fmul_rn(swgt[tp], sum);
+            } else if (MODE == MODE_FUSED) {
+              // whole ray in this tile: prediction, residual, upstream gradient
+              // rounded product (no contraction into the residual), as in the
+              // forward kernel, so both passes produce the same residuals
+              const float pbar = __fmul_rn(a.rays[r].wgt, sum);
+              a.proj[r] = pbar;
+              const float e = pbar - a.meas[r];
+              lossacc += (double)e * (double)e;
+              sg[o0 - tb] = g_scale * e;
+            } else if (o0 < tb) {
+              a.part[2 * t + 0] = sum;
+            } else if (o1 > tb + TILE) {
+              a.part[2 * t + 1] = sum;
+            } else {
+              a.proj[r] = __fmul_rn(a.rays[r].wgt, sum);
+            }
+          }
+        }
+        __syncthreads();
+      }
+      if (BWD_PART) {
+        // ---- adjoint (Eq. (8)): dL/dM = g_r mu0 l_r / n_r, through the output map
+        float dob[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const float z = zo[nb];
+          const float dMdz = a.out_act ? 1.f / (1.f + expf(-z)) : 1.f;
+          float gr = 0.f;
+          if (rid[nb] >= 0) gr = MODE == MODE_FUSED ? sg[poff[nb]] : a.gup[rid[nb]];
+          dob[nb] = gr * wgt[nb] * dMdz;
+        }
+        // output-layer gradient: dw_o = sum_p dob_p h_L,p ; db_o = sum_p dob_p.
+        // Halving butterfly over the 32 lanes of each half, in two passes over
+        // the slots: after 5 steps lane pl holds the sums of KF consecutive slots.
+        {
+          constexpr int K = 32;  // slots per pass (the butterfly needs a multiple of 32)
+#pragma unroll
+          for (int pass = 0; pass < (H / 2) / K; ++pass) {
+            float v[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+              const int rho = pass * K + i;
+              float s = 0.f;
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) s += dob[nb] * T::get(y[nb][rho / VPC], rho % VPC);
+              v[i] = s;
+            }
+#pragma unroll
+            for (int st = 0; st < 5; ++st) {
+              const int o = 16 >> st;
+              const int half = K >> (st + 1);
+              const bool up = (pl & o) != 0;
+#pragma unroll
+              for (int i = 0; i < half; ++i) {
+                const float send = up ? v[i] : v[i + half];
+                const float keep = up ? v[i + half] : v[i];
+                v[i] = keep + __shfl_xor(send, o);
+              }
+            }
+            constexpr int KF = K / 32;
+#pragma unroll
+            for (int i = 0; i < KF; ++i) sdwo[w][feat(pass * K + KF * pl + i, hf)] += v[i];
+          }
+          float sb = 0.f;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) sb += dob[nb];
+#pragma unroll
+          for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
+          if (lane == 0) sdwo[w][H] += sb;
+        }
+        // delta_L = w_o dob . act'(z_L)
+        chunk_t d[NB][CHh];
+        if (ACT == 1) {
+          // Swish: the last layer's derivatives, just stored by this wave
+          wait_vm<0>();
+          const char* ap = (const char*)astash(L - 1) + lane_off((uint32_t)(lane * sizeof(chunk_t)));
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c)
+              d[nb][c] = *(const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t));
+        }
+#pragma unroll
+        for (int c = 0; c < CHh; ++c) {
+          float wv[VPC];
+#pragma unroll
+          for (int e = 0; e < VPC; ++e) wv[e] = wop[VPC * c + e];
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) {
+            float v[VPC];
+            if (ACT == 1) {
+#pragma unroll
+              for (int e = 0; e < VPC; ++e) v[e] = (wv[e] * dob[nb]) * T::get(d[nb][c], e);
+            } else {
+#pragma unroll
+              for (int e = 0; e < VPC; ++e) {
+                // h_L >= 0 (ReLU output): h > 0 iff its bit pattern is non-zero
+                const int hb = __float_as_int(T::get(y[nb][c], e));
+                const int keep = (int)neg_u32((uint32_t)hb) >> 31;  // 0 or all ones
+                v[e] = __int_as_float(__float_as_int(wv[e] * dob[nb]) & keep);
+              }
+            }
+            d[nb][c] = T::from_f32(v);
+          }
+        }
+        auto dstash = [&](int l) { return (chunk_t*)a.stash + a.d_base[l] + blk0 * (CHh * 64); };
+        if (L == 1) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c)
+              T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
+        }
+        // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
+        // call stores its input delta_l for the weight gradient.  Two layers per
+        // iteration with swapped roles, as in the forward.
+        auto adj = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
+          uint32_t mk[MSK_PER_LAYER];
+          if (ACT == 0)
+#pragma unroll
+            for (int k = 0; k < MSK_PER_LAYER; ++k)
+              mk[k] = msk_w[((l - 1) * MSK_PER_LAYER + k) * 64 + lane];
+          const WSrc nx = l > 1 ? WTl(l - 1) : (more ? Wl(0) : none);
+          const int nxb = l > 1 ? PB_H : PB_IN;
+          // entering from the forward's last layer or from the previous adjoint
+          // layer: both stored their last panel's share of a width-H input
+          layer<PREC, CHh, H, ADJ_EPI, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
+              in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z,
+              astash(l - 1));
+        };
+        for (int l = L - 1; l >= 1; l -= 2) {
+          chunk_t t2[NB][CHh];
+          adj(l, d, t2);
+          if (l - 1 >= 1) {
+            adj(l - 1, t2, d);
+          } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+              for (int c = 0; c < CHh; ++c) d[nb][c] = t2[nb][c];
+          }
+        }
+        if (L > 1) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int c = 0; c < CHh; ++c)
+              T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
+        }
       }
     }
   }
@@ -877,7 +1387,7 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
       a.opart[(int64_t)blockIdx.x * (H + 1) + f] = s;
     }
   }
-  if (MODE == MODE_FUSED) {
+  if (MODE == MODE_FUSED || GROUP) {
     sloss[threadIdx.x] = lossacc;
     __syncthreads();
     for (int o = WAVES_PER_WG * 32; o > 0; o >>= 1) {

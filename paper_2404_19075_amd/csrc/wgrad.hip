@@ -81,7 +81,7 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   for (int k = 0; k < TPW; ++k)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
-  float dbacc = 0.f;
+  float dbacc = 0.f, dbcomp = 0.f;  // bias gradient of the split, Kahan-summed
 
   const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
   const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
@@ -153,7 +153,10 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
       float sb = 0.f;
 #pragma unroll
       for (int p = 0; p < BP; ++p) sb += (float)tD[tid * ROW + p];
-      dbacc += sb;
+      const float y = sb - dbcomp;
+      const float t = dbacc + y;
+      dbcomp = (t - dbacc) - y;
+      dbacc = t;
     }
     // K-step outer, tiles inner: a wave's tiles share their row and column
     // fragments (2 x 2 blocks), which are read from LDS once per step

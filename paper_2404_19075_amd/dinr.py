@@ -77,6 +77,7 @@ class Volume(C.Structure):
 class VolumeStats(C.Structure):
     _fields_ = [("bytes", C.c_int64), ("seconds", C.c_double), ("voxels_per_s", C.c_double)]
 PROF_MLP_FWD, PROF_MLP_BWD, PROF_WGRAD, PROF_MLP_FUSED = 0, 1, 2, 3
+PROF_RAYS, PROF_LOSS, PROF_REDUCE = 4, 5, 6
 
 _lib = None
 

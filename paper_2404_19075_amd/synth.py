@@ -162,8 +162,9 @@ def _views(n_views: int, span: float) -> tuple:
 
 def workload(name: str) -> Workload:
     """The workloads: c0 tiny parity case, c1 FP32 parallel beam, c2 the same
-    in BF16, c3 ragged cone beam, c4 serving (weights as c2), and "paper", the
-    paper's own Swish network on the c2 geometry."""
+    in BF16, c3 ragged cone beam, c4 serving (weights as c2), "paper", the
+    paper's own Swish network on the c2 geometry, and "paper_cyl", the same in
+    a cylindrical field of view."""
     if name == "c0":
         th, tt = _views(90, math.pi)
         g = Geometry(kind=0, rows=32, cols=32, n_views=90, pitch_u=3.0 / 32, pitch_v=3.0 / 32,
@@ -201,6 +202,13 @@ def workload(name: str) -> Workload:
         return dataclasses.replace(
             w, name="paper", mlp=MLPSpec(n_freq=128, width=256, depth=5, act=1, out_act=0,
                                          sigma_t=0.1, sigma_s=0.5), seed=1005)
+    if name == "paper_cyl":
+        # the paper's network in the paper's kind of field of view (Sec. II: the
+        # object lies in a cylinder; App. B item 1 normalises coordinates by
+        # its bounds): radius 1, z in [-1, 1], on the c2 geometry and batch
+        w = workload("paper")
+        g = dataclasses.replace(w.geom, fov_kind=1, fov=(1.0, -1.0, 1.0, 0.0, 0.0, 0.0))
+        return dataclasses.replace(w, name="paper_cyl", geom=g, seed=1006)
     raise KeyError(name)
 
 

@@ -1,0 +1,157 @@
+"""Full-size gradients against the FP64 oracle (Eq. (8)).
+
+At the benchmark's batch sizes the oracle cannot evaluate every ray, so each
+test makes the training step's gradient depend on K sampled rays only: the
+measurements of all other rays are set to the device's own predictions,
+which the step reproduces bit for bit, so their residuals -- and with them
+their upstream gradients 2 (pbar - p) / R -- are exactly zero.  The step
+still runs at full size, in the launch configuration the benchmark times
+(every weight-gradient split, every stash chunk, the compensated cross-split
+sums), and its gradient must equal (K / R) times the oracle's gradient of
+the mean squared error over the K rays.  The K rays are spread over the
+whole batch (first and last ray included), so every stash chunk holds some.
+
+Tolerances are the parity tests' (norm-wise relative error per tensor).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2404_19075_amd import dinr
+from paper_2404_19075_amd import synth as S
+
+from helpers import check_grad, log, make_ctx, near_tie, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32, BF16 = 0, 1
+TOL_GRAD = {FP32: 1e-3, BF16: dict(first=5e-2, rest=1.5e-2, all=5e-3)}
+
+
+def spread_pick(R: int, K: int, seed: int) -> np.ndarray:
+    """K distinct rays, one drawn from each of K equal strata of [0, R), with
+    the first and the last ray of the batch among them."""
+    rng = np.random.default_rng(seed)
+    edges = np.linspace(0, R, K + 1).astype(np.int64)
+    pick = np.array([rng.integers(edges[k], edges[k + 1]) for k in range(K)], dtype=np.int64)
+    pick[0], pick[-1] = 0, R - 1
+    return np.unique(pick)
+
+
+def sparse_step_check(w, b, prec, ws, K=128, recompute=False, epoch=None, min_chunks=1,
+                      seed=0):
+    """Runs dinr_step at full size with all but K residuals zero and compares
+    its gradient and loss with the oracle's on the K rays."""
+    R = len(b.idx)
+    ctx = make_ctx(w, b.B, prec, ws_bytes=ws, recompute=recompute)
+    try:
+        return _sparse_step_check(ctx, w, b, prec, K, epoch, min_chunks, seed)
+    finally:
+        ctx.close()  # the workspace is tens of GiB: free it even when a check fails
+        torch.cuda.empty_cache()
+
+
+def _sparse_step_check(ctx, w, b, prec, K, epoch, min_chunks, seed):
+    R = len(b.idx)
+    if epoch is not None:
+        ctx.set_sample_epoch(epoch)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    n = torch.empty(R, dtype=torch.int32, device="cuda")
+    proj = ctx.forward_project(P, idx, n_out=n)
+    pick = spread_pick(R, K, seed)
+    K = len(pick)
+    meas = proj.clone()
+    meas[torch.tensor(pick, device="cuda")] = torch.tensor(b.meas[pick], device="cuda")
+    ctx.profile(True)
+    proj2 = torch.empty(R, device="cuda")
+    grad, _, loss, gnorm = ctx.step(P, idx, meas, proj=proj2)
+    torch.cuda.synchronize()
+    assert ctx.step_status() == dinr.OK
+    _, n_fused = ctx.profile_read(dinr.PROF_MLP_FUSED)
+    _, n_bwd = ctx.profile_read(dinr.PROF_MLP_BWD)
+    _, n_wg = ctx.profile_read(dinr.PROF_WGRAD)
+    ctx.profile(False)
+    chunks = max(n_fused, n_bwd)
+    log(f"  R={R} K={K}: stash chunks {chunks} ({'one-pass' if n_fused else 'two-pass'}), "
+        f"weight-gradient launches {n_wg}")
+    assert chunks >= min_chunks
+    pg = proj.cpu().numpy()
+    assert np.array_equal(pg, proj2.cpu().numpy())
+    # the oracle on the K rays, with the device's sample counts where a
+    # chord length sits on a multiple of the step (counts are compared first)
+    sp = w.sampling if epoch is None else dataclasses.replace(w.sampling, epoch=epoch)
+    n_override = None
+    if w.sampling.mode == 1:
+        assert O.sub_rays(sp) == 1
+        n_g = n.cpu().numpy()[pick]
+        _, n_ref, _, ln = O.forward(w.geom, w.mlp, sp, None, None, b.idx[pick],
+                                    field=(1, (0, 0, 0, 0, 0)))
+        assert np.all((n_g == n_ref) | near_tie(ln / sp.h))
+        n_override = n_g
+    loss_k, grad_k, proj_k = O.step(w.geom, w.mlp, sp, b.B, b.params, b.idx[pick], b.meas[pick],
+                                    n_override=n_override)
+    ep = rel(pg[pick], proj_k)
+    log(f"  sampled proj rel err {ep:.3e}")
+    g = grad.cpu().numpy().astype(np.float64)
+    want = grad_k * (K / R)
+    el = abs(loss.item() - loss_k * K / R) / (loss_k * K / R)
+    log(f"  loss rel err {el:.3e}")
+    worst = check_grad(w, g, want, TOL_GRAD[prec], f"R={R} K={K}")
+    assert el <= (1e-4 if prec == FP32 else 1e-3)
+    gn = float(np.sum(g * g))
+    assert abs(gnorm.item() - gn) <= 1e-9 * gn
+    return worst
+
+
+def test_fullsize_c2_gradient_vs_oracle():
+    """c2 as the benchmark times it: 65,536 rays x 256 samples, BF16, the
+    one-pass step with the whole stash in one chunk (1,024 weight-gradient
+    splits per layer)."""
+    w = S.workload("c2")
+    b = S.make_batch(w)
+    log("full c2 vs oracle")
+    sparse_step_check(w, b, BF16, ws=120 << 30, seed=1)
+
+
+def test_fullsize_c1_fp32_gradient_vs_oracle_chunked():
+    """c1, the FP32 path, at full size: the FP32 stash does not fit a 120 GiB
+    workspace, so the step runs in two or more chunks."""
+    w = S.workload("c1")
+    b = S.make_batch(w)
+    log("full c1 FP32 vs oracle")
+    sparse_step_check(w, b, FP32, ws=120 << 30, min_chunks=2, seed=2)
+
+
+def test_fullsize_c3_gradient_vs_oracle_recompute_chunked():
+    """c3 at full size: 131,072 cone-beam rays with per-ray counts
+    clamp(ceil(l/h), 32, 512), L = 8, the two-pass step recomputing the
+    forward in the backward, over several stash chunks."""
+    w = S.workload("c3")
+    b = S.make_batch(w)
+    log("full c3 vs oracle")
+    sparse_step_check(w, b, BF16, ws=64 << 30, K=64, recompute=True, min_chunks=2, seed=3)
+
+
+def test_fullsize_paper_2x2_random_gradient_vs_oracle():
+    """The paper's network with its sampling at full size: 65,536 projections
+    x 2 x 2 rays x 256 randomly placed samples (Appendix A, Sec. IV), the
+    two-pass step over several stash chunks, at one (seed, epoch)."""
+    w0 = S.workload("paper")
+    w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, sub=2, jitter=1,
+                                                             seed=31))
+    b = S.make_batch(w)
+    log("full paper 2x2 random vs oracle")
+    sparse_step_check(w, b, BF16, ws=96 << 30, K=64, epoch=12, min_chunks=2, seed=4)
+
+
+def test_fullsize_paper_cylinder_gradient_vs_oracle():
+    """The paper's network in the paper's cylindrical field of view (Sec. II,
+    App. B item 1) at full size, one-pass step."""
+    w = S.workload("paper_cyl")
+    b = S.make_batch(w)
+    log("full paper network, cylindrical FOV, vs oracle")
+    sparse_step_check(w, b, BF16, ws=120 << 30, seed=5)

@@ -2,8 +2,16 @@
 
 Tolerances (norm-wise relative error, ||x - x_ref|| / ||x_ref||):
   FP32 path: projections 1e-4, every gradient tensor 1e-3, loss 1e-4
-  BF16 path: projections 2e-2 (gradients and loss are reported and held to a
-             loose sanity bound of 5e-2)
+  BF16 path: projections 2e-2; the whole gradient 5e-3, each tensor of the
+             first layer (W1, b1) 5e-2, every other tensor 1.5e-2; loss 1e-3.
+             The largest errors measured over these cases and the full-size
+             ones are 2.6e-3 (whole gradient), 2.0e-2 (W1), 7.5e-3 (other
+             tensors) and 8e-5 (loss).  The first layer's gradient sums
+             products with high-frequency Fourier features that cancel
+             heavily along a ray, so every rounding of the BF16 operands and
+             every ReLU unit whose pre-activation rounds across zero is
+             amplified there; the FP32 path shows the same 40-fold
+             amplification of W1's error over the other tensors.
 Sample counts are integers and must match exactly wherever the chord length
 is not within 1e-4 (relative) of a multiple of the step; the oracle is then
 re-run with the GPU's counts so that projections are compared on equal
@@ -17,14 +25,16 @@ import pytest
 from oracle import oracle as O
 from paper_2404_19075_amd import synth as S
 
-from helpers import log, make_ctx, param_slices, rel, small_workload
+from helpers import (check_grad, log, make_ctx, near_tie, rel, resolve_counts,
+                     small_workload)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP32, BF16 = 0, 1
 TOL_PROJ = {FP32: 1e-4, BF16: 2e-2}
-TOL_GRAD = {FP32: 1e-3, BF16: 5e-2}
+TOL_GRAD = {FP32: 1e-3, BF16: dict(first=5e-2, rest=1.5e-2, all=5e-3)}
+TOL_LOSS = {FP32: 1e-4, BF16: 1e-3}
 
 
 def run_forward(w, batch, prec, epoch=None):
@@ -68,16 +78,6 @@ def oracle_step(key, w, b, n_override=None):
     return _ORACLE[key]
 
 
-def check_grad(w, g, ref, tol, label):
-    worst = 0.0
-    for name, sl in param_slices(w.mlp):
-        e = rel(g[sl], ref[sl])
-        worst = max(worst, e)
-        log(f"  {label} {name}: rel err {e:.3e}")
-        assert e <= tol, (label, name, e)
-    return worst
-
-
 @pytest.mark.parametrize("prec", [FP32, BF16])
 def test_forward_c0(prec):
     b = S.make_batch("c0")
@@ -102,7 +102,7 @@ def test_step_c0(prec):
     el = abs(out["loss"] - loss) / loss
     log(f"  proj {ep:.3e} loss {el:.3e} (gpu {out['loss']:.6e} oracle {loss:.6e})")
     assert ep <= TOL_PROJ[prec]
-    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    assert el <= TOL_LOSS[prec]
     check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c0 prec={prec}")
     gn = float(np.sum(out["grad"].astype(np.float64) ** 2))
     assert abs(out["gnorm"] - gn) <= 1e-9 * gn
@@ -150,21 +150,51 @@ def test_cone_ragged_subset(prec):
     check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 prec={prec}")
 
 
-def test_adam_update_c0():
-    b = S.make_batch("c0")
-    w = b.workload
+def test_adam_two_steps_c0():
+    """Two training steps with Adam (Sec. II, App. C) on two c0 batches.  After
+    each step the device's first and second moments equal the oracle's Adam
+    recursion applied to the oracle's gradient (taken at the parameters the
+    device started the step from), and the device's parameters moved by
+    exactly the bias-corrected update of its own moments.  After the first
+    step the parameters also equal the oracle's.  The second step exercises
+    the moment decay and the bias correction beyond the first step."""
+    from paper_2404_19075_amd import dinr
+    w = S.workload("c0")
+    b1_ = S.make_batch(w)
+    b2_ = S.make_batch(w, seed_offset=1)
+    lr, beta1, beta2, eps = 1e-3, 0.9, 0.999, 1e-8
+    ctx = make_ctx(w, b1_.B, FP32)
+    P = torch.tensor(b1_.params, device="cuda")
     m = torch.zeros(w.mlp.n_params, device="cuda")
     v = torch.zeros(w.mlp.n_params, device="cuda")
-    out = run_step(w, b, FP32, adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, 1))
-    _, grad, _ = oracle_step("c0", w, b)
-    p = b.params.astype(np.float64)
-    mm, vv = np.zeros_like(p), np.zeros_like(p)
-    O.adam(p, grad, mm, vv, 1e-3, 0.9, 0.999, 1e-8, 1)
-    # step 1 moves each weight by ~lr sign(g): compare where |g| is not tiny
-    mask = np.abs(grad) > 1e-6 * np.abs(grad).max()
-    err = np.abs(out["params"].astype(np.float64) - p)[mask].max()
-    log(f"  adam max abs err {err:.3e} on {mask.sum()} params")
-    assert err <= 1e-6
+    p_dev = b1_.params.astype(np.float64)
+    mo, vo = np.zeros_like(p_dev), np.zeros_like(p_dev)
+    for k, bk in ((1, b1_), (2, b2_)):
+        _, gk, _ = O.step(w.geom, w.mlp, w.sampling, bk.B, p_dev, bk.idx, bk.meas)
+        po = p_dev.copy()
+        O.adam(po, gk, mo, vo, lr, beta1, beta2, eps, k)
+        ctx.step(P, torch.tensor(bk.idx, device="cuda"), torch.tensor(bk.meas, device="cuda"),
+                 adam=(m, v, lr, beta1, beta2, eps, k))
+        torch.cuda.synchronize()
+        assert ctx.step_status() == dinr.OK
+        pd, md, vd = (t.cpu().numpy().astype(np.float64) for t in (P, m, v))
+        # m is linear and v quadratic in the gradient, whose FP32 error is a
+        # few 1e-6 norm-wise on c0
+        em, ev = rel(md, mo), rel(vd, vo)
+        # the update of the device's own moments, in FP64
+        upd = lr * (md / (1 - beta1 ** k)) / (np.sqrt(vd / (1 - beta2 ** k)) + eps)
+        eu = np.abs((p_dev - upd) - pd).max()
+        log(f"  step {k}: m rel {em:.2e} v rel {ev:.2e}, update vs own moments max abs {eu:.2e}")
+        assert em <= 1e-4 and ev <= 1e-4
+        assert eu <= 2e-8  # a few roundings of parameters of magnitude <= 1/8
+        if k == 1:
+            # a weight moves by ~lr sign(g): compare where |g| is not tiny
+            mask = np.abs(gk) > 1e-6 * np.abs(gk).max()
+            ep = np.abs(pd - po)[mask].max()
+            log(f"  step 1 parameters vs the oracle: max abs {ep:.2e} on {mask.sum()}")
+            assert ep <= 1e-6
+        p_dev = pd
+    ctx.close()
 
 
 def test_edges_misses_bad_indices_and_small_batches():
@@ -439,7 +469,7 @@ def test_swish_c0_step(prec):
     el = abs(out["loss"] - loss) / loss
     log(f"  proj {ep:.3e} forward {ef:.3e} loss {el:.3e}")
     assert ep <= TOL_PROJ[prec] and ef <= TOL_PROJ[prec]
-    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    assert el <= TOL_LOSS[prec]
     check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"swish c0 prec={prec}")
     assert out["status"] == 0
 
@@ -494,7 +524,7 @@ def test_subpixel_rays_c0(prec):
     ep2, el = rel(out["proj"], proj), abs(out["loss"] - loss) / loss
     log(f"  step proj {ep2:.3e} loss {el:.3e}")
     assert ep2 <= TOL_PROJ[prec]
-    assert el <= (1e-4 if prec == FP32 else 5e-2)
+    assert el <= TOL_LOSS[prec]
     check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c0 D=2 prec={prec}")
 
 
@@ -515,15 +545,19 @@ def test_subpixel_rays_cone_variable_counts(prec):
     log(f"  projections {len(n_g)}, count mismatches {int((~same).sum())}, near ties {int(tie.sum())}")
     assert np.all(same | tie)
     assert np.any(n_ref.reshape(-1, 4).min(axis=1) != n_ref.reshape(-1, 4).max(axis=1))
-    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx)
-    ep = rel(proj_g[same], ref[same])
+    # the oracle with per-ray counts that reproduce the device's totals
+    n_ov = resolve_counts(n_g, n_ref, q, 4)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, n_override=n_ov)
+    ep = rel(proj_g, ref)
     log(f"  proj rel err {ep:.3e}")
     assert ep <= TOL_PROJ[prec]
-    if np.all(same):
-        out = run_step(w, b, prec)
-        loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas)
-        log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e}")
-        check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 D=2 prec={prec}")
+    out = run_step(w, b, prec)
+    loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx, b.meas,
+                           n_override=n_ov)
+    el = abs(out["loss"] - loss) / loss
+    log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e} ({el:.2e})")
+    assert el <= TOL_LOSS[prec]
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"c3 D=2 prec={prec}")
 
 
 @pytest.mark.parametrize("prec", [FP32, BF16])
@@ -557,20 +591,30 @@ def test_random_sample_positions_c0(prec):
 
 
 def test_random_positions_subpixel_cone_bf16():
-    """Random positions with D = 2 and per-ray counts on the c3 cone beam."""
+    """Random positions with D = 2 and per-ray counts on the c3 cone beam:
+    counts differ from the oracle's only at near ties, projections and the
+    two-pass step's gradient match the oracle at the same (seed, epoch)."""
     w0 = small_workload("c3", 32)
     w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, sub=2, jitter=1,
                                                              seed=99))
     b = S.make_batch(w)
     proj_g, n_g = run_forward(w, b, BF16, epoch=3)
     spe = dataclasses.replace(w.sampling, epoch=3)
-    ref, n_ref, _, _ = O.forward(w.geom, w.mlp, spe, b.B, b.params, b.idx)
+    _, n_ref, _, ln = O.forward(w.geom, w.mlp, spe, None, None, b.idx, field=(1, (0, 0, 0, 0, 0)))
+    q = ln / w.sampling.h
     same = n_g == n_ref.reshape(-1, 4).sum(axis=1)
-    log(f"  count mismatches {int((~same).sum())}")
-    assert same.mean() > 0.9
-    ep = rel(proj_g[same], ref[same])
+    log(f"  count mismatches {int((~same).sum())}, near ties {int(near_tie(q).sum())}")
+    n_ov = resolve_counts(n_g, n_ref, q, 4)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, spe, b.B, b.params, b.idx, n_override=n_ov)
+    ep = rel(proj_g, ref)
     log(f"  proj rel err {ep:.3e}")
     assert ep <= TOL_PROJ[BF16]
+    out = run_step(w, b, BF16, epoch=3)
+    loss, grad, _ = O.step(w.geom, w.mlp, spe, b.B, b.params, b.idx, b.meas, n_override=n_ov)
+    el = abs(out["loss"] - loss) / loss
+    log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e} ({el:.2e})")
+    assert el <= TOL_LOSS[BF16]
+    check_grad(w, out["grad"], grad, TOL_GRAD[BF16], "c3 D=2 jitter")
 
 
 def test_subpixel_edges_misses_bad_indices_and_ray_limit():
@@ -608,6 +652,251 @@ def test_subpixel_edges_misses_bad_indices_and_ray_limit():
     assert rc == dinr.EINVAL
     assert "exceeds" in ctx._lib.dinr_last_error(ctx._h).decode()
     ctx.close()
+
+
+def paper_sampling(w, D=2, n=256, jitter=1, seed=31):
+    return dataclasses.replace(w, sampling=dataclasses.replace(w.sampling, n=n, sub=D,
+                                                               jitter=jitter, seed=seed))
+
+
+def step_kinds(w, b, prec, recompute=False, epoch=None):
+    """run_step plus the launches of each MLP kernel class it made."""
+    from paper_2404_19075_amd import dinr
+    ctx = make_ctx(w, b.B, prec, recompute=recompute)
+    if epoch is not None:
+        ctx.set_sample_epoch(epoch)
+    ctx.profile(True)
+    P = torch.tensor(b.params, device="cuda")
+    idx = torch.tensor(b.idx, device="cuda")
+    meas = torch.tensor(b.meas, device="cuda")
+    proj = torch.empty(len(b.idx), dtype=torch.float32, device="cuda")
+    grad, proj, loss, _ = ctx.step(P, idx, meas, proj=proj)
+    torch.cuda.synchronize()
+    kinds = {k: ctx.profile_read(v)[1] for k, v in (("fwd", dinr.PROF_MLP_FWD),
+                                                    ("bwd", dinr.PROF_MLP_BWD),
+                                                    ("one_pass", dinr.PROF_MLP_FUSED))}
+    out = dict(grad=grad.cpu().numpy(), proj=proj.cpu().numpy(), loss=float(loss.item()),
+               status=ctx.step_status(), kinds=kinds)
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_grouped_one_pass_step_paper_sampling(prec):
+    """The paper's network with its sampling (App. A: 2 x 2 rays per projection;
+    Sec. IV: random positions; 256 samples per ray) on 160 projections: the
+    one-pass step over groups of tiles that hold one projection each (BF16:
+    four tiles of one ray each; FP32: eight tiles, two per ray) gives the
+    two-pass step's projections bit for bit and its gradient to rounding,
+    and matches the oracle at the same (seed, epoch)."""
+    w = paper_sampling(small_workload("paper", 160))
+    b = S.make_batch(w)
+    log(f"test_grouped_one_pass_step_paper_sampling prec={prec}")
+    o1 = step_kinds(w, b, prec, epoch=7)
+    o2 = step_kinds(w, b, prec, recompute=True, epoch=7)
+    log(f"  kernels: one-pass step {o1['kinds']}, two-pass step {o2['kinds']}")
+    # one launch per stash chunk
+    assert o1["kinds"]["one_pass"] >= 1 and o1["kinds"]["fwd"] == 0 and o1["kinds"]["bwd"] == 0
+    assert o2["kinds"]["one_pass"] == 0 and o2["kinds"]["bwd"] >= 1
+    eg = rel(o1["grad"], o2["grad"])
+    log(f"  one-pass vs two-pass: proj equal {np.array_equal(o1['proj'], o2['proj'])}, "
+        f"grad rel diff {eg:.2e}, loss {o1['loss']:.12e} {o2['loss']:.12e}")
+    assert np.array_equal(o1["proj"], o2["proj"])
+    assert eg <= 1e-6
+    assert abs(o1["loss"] - o2["loss"]) <= 1e-12 * o2["loss"]
+    spe = dataclasses.replace(w.sampling, epoch=7)
+    loss, grad, proj = O.step(w.geom, w.mlp, spe, b.B, b.params, b.idx, b.meas)
+    ep, el = rel(o1["proj"], proj), abs(o1["loss"] - loss) / loss
+    log(f"  vs oracle: proj {ep:.3e} loss {el:.3e}")
+    assert ep <= TOL_PROJ[prec] and el <= TOL_LOSS[prec]
+    check_grad(w, o1["grad"], grad, TOL_GRAD[prec], f"grouped paper prec={prec}")
+    assert o1["status"] == 0
+
+
+def test_grouped_one_pass_step_edges():
+    """The grouped one-pass step (Swish c0 network, 2 x 2 rays of 256 samples,
+    FP32: groups of eight 128-point tiles) on projections whose sub-rays
+    partly miss the field of view (their rays padded with points of weight
+    0), one that misses entirely (prediction 0) and an out-of-range index
+    (NaN): the projections equal the two-pass step's and the oracle's, the
+    loss is not finite and Adam is skipped; without the bad index the
+    gradient matches the two-pass step's and the oracle's."""
+    w0 = swish_c0()
+    w = paper_sampling(w0, n=256, jitter=0)
+    b = S.make_batch(w, n_rays=24)
+    g = w.geom
+    # view 0, row 16: col 0 lies at u = -1.45, outside the box, so its whole
+    # pixel misses; col 5 lies at u = -0.98: of its sub-rays at u = -1.01 and
+    # -0.96 one pair misses
+    edge = np.array([16 * g.cols + 5, 16 * g.cols + 0], dtype=np.int64)
+    idx = np.concatenate([edge, b.idx]).astype(np.int64)
+    meas = np.concatenate([[0.3, 0.2], b.meas]).astype(np.float32)
+    bb = dataclasses.replace(b, idx=idx, meas=meas)
+    _, n_ref, _, _ = O.forward(w.geom, w.mlp, w.sampling, None, None, idx[:2],
+                               field=(1, (0, 0, 0, 0, 0)))
+    log(f"  edge sub-ray counts {n_ref.reshape(2, 4).tolist()}")
+    assert n_ref[:4].min() == 0 and n_ref[:4].max() > 0 and n_ref[4:].max() == 0
+    o1 = step_kinds(w, bb, FP32)
+    o2 = step_kinds(w, bb, FP32, recompute=True)
+    assert o1["kinds"]["one_pass"] >= 1 and o1["kinds"]["bwd"] == 0
+    assert np.array_equal(o1["proj"], o2["proj"]) and o1["proj"][1] == 0.0
+    assert rel(o1["grad"], o2["grad"]) <= 1e-6
+    loss, grad, proj = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, idx, meas)
+    assert rel(o1["proj"], proj) <= TOL_PROJ[FP32]
+    check_grad(w, o1["grad"], grad, TOL_GRAD[FP32], "grouped edges")
+    # an out-of-range index: NaN prediction and loss, Adam skipped
+    bad = dataclasses.replace(bb, idx=np.concatenate([[g.n_proj + 3], idx]).astype(np.int64),
+                              meas=np.concatenate([[0.0], meas]).astype(np.float32))
+    m = torch.zeros(w.mlp.n_params, device="cuda")
+    v = torch.zeros(w.mlp.n_params, device="cuda")
+    o3 = run_step(w, bad, FP32, adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, 1))
+    log(f"  bad index: proj[0] {o3['proj'][0]}, loss {o3['loss']}, status {o3['status']}")
+    assert np.isnan(o3["proj"][0]) and not np.isfinite(o3["loss"])
+    assert o3["status"] == -4 and np.array_equal(o3["params"], b.params)
+    assert np.array_equal(o3["proj"][1:], o1["proj"])
+
+
+def cylinder(w, radius=1.0, z0=-1.0, z1=1.0):
+    """The workload in a cylindrical field of view (Sec. II, App. A): radius
+    `radius` about the z axis, z in [z0, z1]; its bounds normalise x, y and z
+    (App. B item 1)."""
+    return dataclasses.replace(w, geom=dataclasses.replace(
+        w.geom, fov_kind=1, fov=(radius, z0, z1, 0.0, 0.0, 0.0)))
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+@pytest.mark.parametrize("D", [1, 2])
+def test_cylinder_fov_parallel_c0(prec, D):
+    """c0 parallel beam in a cylindrical FOV of radius 1, z in [-1, 1]: counts
+    (n or 0 per ray), projections and the step's loss and gradient match the
+    oracle; at view 0 a pixel whose ray passes outside the radius and one
+    whose ray passes above the z-slab give n = 0 and projection 0."""
+    w = with_sub(cylinder(S.workload("c0")), D)
+    b = S.make_batch(w)
+    g = w.geom
+    log(f"test_cylinder_fov_parallel_c0 prec={prec} D={D}")
+    # view 0, row 16 (v = 0.047), col 0 (u = -1.45): outside the radius;
+    # row 0 (v = -1.45), col 16 (u = 0.047): outside the z-slab
+    radial, slab = 16 * g.cols + 0, 0 * g.cols + 16
+    idx = np.concatenate([[radial, slab], b.idx]).astype(np.int64)
+    bb = dataclasses.replace(b, idx=idx, meas=np.concatenate([[0.0, 0.0], b.meas]).astype(np.float32))
+    proj_g, n_g = run_forward(w, bb, prec)
+    ref, n_ref, _, ln = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, idx)
+    assert n_g[0] == 0 and n_g[1] == 0 and proj_g[0] == 0.0 and proj_g[1] == 0.0
+    assert np.array_equal(n_g, n_ref.reshape(len(idx), -1).sum(axis=1))
+    assert np.any(ln.reshape(len(idx), -1)[2:] < 1.9)  # chords shorter than the box's
+    ep = rel(proj_g, ref)
+    log(f"  forward proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[prec]
+    out = run_step(w, bb, prec)
+    loss, grad, proj = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, idx, bb.meas)
+    ep2, el = rel(out["proj"], proj), abs(out["loss"] - loss) / loss
+    log(f"  step proj {ep2:.3e} loss {el:.3e}")
+    assert ep2 <= TOL_PROJ[prec] and el <= TOL_LOSS[prec]
+    check_grad(w, out["grad"], grad, TOL_GRAD[prec], f"cylinder c0 D={D} prec={prec}")
+
+
+@pytest.mark.parametrize("D", [1, 2])
+def test_cylinder_fov_cone_per_ray_counts(D):
+    """c3 cone beam (magnification 2) in a cylindrical FOV with per-ray counts
+    n = clamp(ceil(l/h), 32, 512) from the cylinder chords, BF16: counts match
+    the oracle except at near ties, projections and the two-pass step's
+    gradient match it with the device's counts; rays missing through the
+    radius and through the z-slab give 0."""
+    w = with_sub(cylinder(small_workload("c3", 48)), D)
+    b = S.make_batch(w)
+    g = w.geom
+    log(f"test_cylinder_fov_cone_per_ray_counts D={D}")
+    # view 0: row 256 (v ~ 0), col 0 (u = -3.0, -1.5 at the axis): outside the
+    # radius; row 0, col 256: outside the z-slab
+    radial, slab = 256 * g.cols + 0, 0 * g.cols + 256
+    idx = np.concatenate([[radial, slab], b.idx]).astype(np.int64)
+    bb = dataclasses.replace(b, idx=idx, meas=np.concatenate([[0.0, 0.0], b.meas]).astype(np.float32))
+    proj_g, n_g = run_forward(w, bb, BF16)
+    _, n_ref, _, ln = O.forward(w.geom, w.mlp, w.sampling, None, None, idx,
+                                field=(1, (0, 0, 0, 0, 0)))
+    q = ln / w.sampling.h
+    D2 = D * D
+    assert n_g[0] == 0 and n_g[1] == 0 and proj_g[0] == 0.0 and proj_g[1] == 0.0
+    nr = n_ref.reshape(len(idx), D2)
+    log(f"  count range {nr[2:].min()}..{nr[2:].max()}, mismatches "
+        f"{int(np.sum(n_g != nr.sum(axis=1)))}, near ties {int(near_tie(q).sum())}")
+    hit = nr[2:][nr[2:] > 0]
+    assert hit.min() >= 32 and hit.max() > 32
+    n_ov = resolve_counts(n_g, n_ref, q, D2)
+    ref, _, _, _ = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, idx, n_override=n_ov)
+    ep = rel(proj_g, ref)
+    log(f"  proj rel err {ep:.3e}")
+    assert ep <= TOL_PROJ[BF16]
+    out = run_step(w, bb, BF16)
+    loss, grad, _ = O.step(w.geom, w.mlp, w.sampling, b.B, b.params, idx, bb.meas,
+                           n_override=n_ov)
+    el = abs(out["loss"] - loss) / loss
+    log(f"  loss gpu {out['loss']:.6e} oracle {loss:.6e} ({el:.2e})")
+    assert el <= TOL_LOSS[BF16]
+    check_grad(w, out["grad"], grad, TOL_GRAD[BF16], f"cylinder cone D={D}")
+
+
+def test_c1_network_ray_subset_chunked():
+    """The c1 network on 160 rays with a workspace that holds a third of the
+    stash: the step's adjoint runs in three chunks and still matches the
+    oracle."""
+    w = small_workload("c1", 160)
+    b = S.make_batch(w)
+    loss, grad, proj = oracle_step("c1-160", w, b)
+    for prec in (FP32, BF16):
+        ctx = make_ctx(w, b.B, prec, ws_bytes=(128 << 20) * (2 if prec == FP32 else 1))
+        ctx.profile(True)
+        P = torch.tensor(b.params, device="cuda")
+        idx = torch.tensor(b.idx, device="cuda")
+        meas = torch.tensor(b.meas, device="cuda")
+        pr = torch.empty(len(b.idx), device="cuda")
+        g, _, l_d, _ = ctx.step(P, idx, meas, proj=pr)
+        torch.cuda.synchronize()
+        # adjoint launches, one per chunk (one-pass BF16; the FP32 tile of 128
+        # points cannot hold a 256-sample ray, so FP32 takes the two-pass step)
+        chunks = max(ctx.profile_read(3)[1], ctx.profile_read(1)[1])
+        ep = rel(pr.cpu().numpy(), proj)
+        el = abs(l_d.item() - loss) / loss
+        log(f"  prec={prec}: chunks {chunks}, proj {ep:.3e}, loss {el:.3e}")
+        assert chunks == 3
+        assert ep <= TOL_PROJ[prec] and el <= TOL_LOSS[prec]
+        check_grad(w, g.cpu().numpy(), grad, TOL_GRAD[prec], f"c1 chunked prec={prec}")
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FP32, BF16])
+def test_compensated_ray_sum_of_long_rays(prec):
+    """Eq. (1)'s sum over many samples: four rays of 2^20 samples each (c0
+    network).  A plain sequential FP32 sum of the oracle's own per-sample
+    values misses the oracle's FP64 sum by far more than the device does: the
+    kernel's ray-sum (a compensated scan within each 256-point tile, Kahan
+    over the tiles) meets the oracle to within the rounding of the samples
+    themselves."""
+    w0 = S.workload("c0")
+    w = dataclasses.replace(w0, sampling=dataclasses.replace(w0.sampling, n=1 << 20))
+    b = S.make_batch(w, n_rays=4)
+    proj_g, n_g = run_forward(w, b, prec)
+    ref, n_ref, s_in, ln = O.forward(w.geom, w.mlp, w.sampling, b.B, b.params, b.idx)
+    assert np.array_equal(n_g, n_ref)
+    n = w.sampling.n
+    naive_err, gpu_err = [], []
+    for r, i in enumerate(b.idx):
+        o, d, t = O.ray(w.geom, int(i))
+        s = s_in[r] + (np.arange(n) + 0.5) * (ln[r] / n)
+        pts = np.concatenate([o[None, :] + s[:, None] * d[None, :], np.full((n, 1), t)], axis=1)
+        vals = O.field_points(w.geom, w.mlp, b.B, b.params, pts)  # mu0 M of every sample
+        exact = float(np.sum(vals)) * (ln[r] / n)
+        naive = float(np.cumsum(vals.astype(np.float32), dtype=np.float32)[-1]) * (ln[r] / n)
+        naive_err.append(abs(naive - exact) / abs(exact))
+        gpu_err.append(abs(float(proj_g[r]) - ref[r]) / abs(ref[r]))
+        assert abs(exact - ref[r]) <= 1e-12 * abs(ref[r])
+    log(f"  prec={prec}: sequential FP32 sum rel err {max(naive_err):.2e}, "
+        f"device {max(gpu_err):.2e}")
+    bound = 2e-6 if prec == FP32 else TOL_PROJ[BF16]
+    assert max(gpu_err) <= bound
+    if prec == FP32:
+        assert min(naive_err) > 3 * bound
 
 
 def test_training_on_c0_reduces_the_loss_tenfold():

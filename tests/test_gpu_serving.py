@@ -93,6 +93,43 @@ def test_reprojection_matches_oracle_projection(prec, S_):
     ctx.close()
 
 
+def test_largest_requests_c2_sampled():
+    """The largest requests of the serving mix on the c2 network (2C = H = 256,
+    six layers, BF16): a 512 x 512 reprojection with 256 samples per ray (67 M
+    samples) and a 512 x 512 slice, submitted together; 256 sampled pixels of
+    each match the oracle (forward projection of the same rays, field at the
+    same points)."""
+    from paper_2404_19075_amd import dinr
+    b = S.make_batch("c2", n_rays=8)
+    w = b.workload
+    ctx, P, srv = server_for(w, b, BF16, budget=1 << 30)
+    n, theta, t, z = 512, 2.3, 0.61, -0.27
+    rp = torch.empty(n * n, device="cuda")
+    sl = torch.empty(n * n, device="cuda")
+    t0 = time.perf_counter()
+    tk1 = srv.submit(dinr.QUERY_REPROJECTION, n, theta, t, rp, samples_per_ray=256)
+    tk2 = srv.submit(dinr.QUERY_SLICE, n, z, t, sl)
+    srv.wait(tk1)
+    srv.wait(tk2)
+    log(f"  512^2 reprojection + slice served in {time.perf_counter() - t0:.3f} s")
+    pick = np.random.default_rng(11).choice(n * n, 256, replace=False)
+    g1 = reprojection_geometry(w.geom, n, theta, t)
+    ref, nref, _, _ = O.forward(g1, w.mlp, S.Sampling(mode=0, n=256), b.B, b.params, pick)
+    got = rp.cpu().numpy()[pick]
+    miss = nref == 0
+    e = rel(got, ref)
+    log(f"  reprojection: {int(miss.sum())} of 256 sampled rays miss, rel err {e:.3e}")
+    assert np.all(got[miss] == 0)
+    assert e <= TOL[BF16]
+    pts = slice_points(w.geom, n, z, t)[pick]
+    ref_s = O.field_points(w.geom, w.mlp, b.B, b.params, pts)
+    es = rel(sl.cpu().numpy()[pick], ref_s)
+    log(f"  slice: rel err {es:.3e}")
+    assert es <= TOL[BF16]
+    srv.close()
+    ctx.close()
+
+
 def test_alone_equals_mix_bitwise():
     from paper_2404_19075_amd import dinr
     b = S.make_batch("c0", n_rays=8)
