@@ -135,15 +135,26 @@ def serving(batch, params_np, n_req=1000, rates=(0.1, 0.5, 1.0, 2.0), n_cap=200,
         srv.wait(tk)
         srv.release(tk)
     reqs = [draw() for _ in range(n_cap)]
+    st0 = srv.stats()
     t0 = time.perf_counter()
     tks = [submit(k, r) for k, r in enumerate(reqs)]
     for tk in tks:
         srv.wait(tk)
-    cap = len(reqs) / (time.perf_counter() - t0)
+    span = time.perf_counter() - t0
+    cap = len(reqs) / span
+    st1 = srv.stats()
     for tk in tks:
         srv.release(tk)
-    log(f"serving capacity {cap:.2f} req/s ({n_cap} requests)")
+    # forward FLOP the batch made the matrix cores do: every point of every
+    # tile run (256 points per tile, padding and rays outside the field of
+    # view included)
+    tiles = st1["tiles"] - st0["tiles"]
+    fwd_flop = tiles * 256 * w.mlp.fwd_flops_per_point()
+    log(f"serving capacity {cap:.2f} req/s ({n_cap} requests, {tiles} tiles, "
+        f"{st1['launches'] - st0['launches']} launches, {fwd_flop / span / 1e12:.0f} TFLOP/s)")
     out = dict(capacity_req_per_s=cap, capacity_requests=n_cap,
+               capacity_tiles=tiles, capacity_launches=st1["launches"] - st0["launches"],
+               capacity_fwd_tflops=fwd_flop / span / 1e12,
                mix="50% slices n=64..512, 50% reprojections n=128..512 x 256 samples",
                mem_budget_bytes=1 << 30, max_active=64, rates=[])
     for frac in rates:
