@@ -57,6 +57,7 @@ struct Plan {
   void* stash = nullptr;
   int64_t chunk_points = 0, n_chunks = 0, kb = 0, splits_per_chunk = 0;
   int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS], a_base[MAX_LAYERS];
+  int64_t dob_base = 0, m_base = 0;
   float* wpart = nullptr;
   float* opart = nullptr;
   double* lpart = nullptr;
@@ -156,11 +157,18 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   // are allocated for it); raised below once the chunk size is known
   const int64_t k_split = 16384;
   p->kb = k_split / 32;
-  int64_t per_point = 0;  // stash elements per point
-  // layer 1's input is stashed as the point's 4 coordinates (16 bytes)
-  for (int l = 0; l < c->L; ++l) per_point += (l == 0 ? 16 / (int)esize(c->prec) : c->H) + c->H;
-  // Swish: the activation derivative of every hidden output as well
-  if (c->mlp.act == DINR_SWISH) per_point += (int64_t)c->L * c->H;
+  // stash bytes per point: layer 1's input as the point's 4 coordinates (16
+  // bytes), h_1 .. h_{L-1} and delta_1 .. delta_{L-1}; delta_L (L >= 2) as
+  // dL/dz_o (4 bytes) and, ReLU, the last layer's mask bits (32 bytes per
+  // point at H = 256, one 16-byte chunk per lane and 32-point block); Swish: the
+  // activation derivative of every hidden output as well
+  const int64_t hb = (int64_t)c->H * esize(c->prec);
+  const bool compact = c->L >= 2;
+  int64_t per_point = 16;
+  for (int l = 1; l < c->L; ++l) per_point += hb;
+  per_point += (int64_t)(compact ? c->L - 1 : c->L) * hb;
+  if (compact) per_point += 4 + (c->mlp.act == DINR_SWISH ? 0 : 32);
+  if (c->mlp.act == DINR_SWISH) per_point += (int64_t)c->L * hb;
   const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
   const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
   const int64_t total_splits = pts_pad / k_split;
@@ -176,7 +184,7 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
     const int64_t n_chunks = (pts_pad + chunk - 1) / chunk;
     p->opart = A.take<float>((size_t)n_chunks * p->grid_mlp * (c->H + 1));
     p->lpart = A.take<double>((size_t)n_chunks * p->grid_mlp);
-    p->stash = A.take<char>((size_t)chunk * per_point * esize(c->prec));
+    p->stash = A.take<char>((size_t)chunk * per_point);
     if (A.ok) {
       p->chunk_points = chunk;
       p->n_chunks = n_chunks;
@@ -197,17 +205,24 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   // stash region of each layer: h blocks then delta blocks, in 16-byte chunks
   int64_t base = 0;
   const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
+  const int64_t blocks = p->chunk_points / 32;
   for (int l = 0; l < c->L; ++l) {
     p->h_base[l] = base;
     // layer 1: one 16-byte chunk of coordinates per point
-    base += l == 0 ? p->chunk_points : (p->chunk_points / 32) * (c->H / vpc2) * 64;
+    base += l == 0 ? p->chunk_points : blocks * (c->H / vpc2) * 64;
     p->d_base[l] = base;
-    base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
+    if (!(compact && l == c->L - 1)) base += blocks * (c->H / vpc2) * 64;
   }
   for (int l = 0; l < c->L; ++l) {
     p->a_base[l] = base;
-    if (c->mlp.act == DINR_SWISH) base += (p->chunk_points / 32) * (c->H / vpc2) * 64;
+    if (c->mlp.act == DINR_SWISH) base += blocks * (c->H / vpc2) * 64;
   }
+  // delta_L's substitutes: 32 floats (8 chunks) of dL/dz_o and, ReLU, 64 mask
+  // chunks per block
+  p->dob_base = base;
+  if (compact) base += blocks * 8;
+  p->m_base = base;
+  if (compact && c->mlp.act != DINR_SWISH) base += blocks * 64;
   return DINR_OK;
 }
 
@@ -304,6 +319,8 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       a.d_base[l] = p.d_base[l];
       a.a_base[l] = p.a_base[l];
     }
+    a.dob_base = p.dob_base;
+    a.m_base = p.m_base;
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);
     {
       ProfScope ps(c, mode == MODE_BWD ? DINR_PROF_MLP_BWD : DINR_PROF_MLP_FUSED, st);
@@ -322,6 +339,11 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       w.h_base = p.h_base[l];
       w.coords = l == 0;
       w.Bmat = c->d_B;
+      // the last layer's delta is rebuilt (L >= 2)
+      w.dmode = (c->L >= 2 && l == c->L - 1) ? (c->mlp.act == DINR_SWISH ? 2 : 1) : 0;
+      w.dob_base = p.dob_base;
+      w.m_base = c->mlp.act == DINR_SWISH ? p.a_base[l] : p.m_base;
+      w.wo = params + c->wo_off;
       w.wpart = p.wpart;
       w.split_base = ch * p.splits_per_chunk;
       w.nh = c->nh;

@@ -94,6 +94,11 @@ struct MlpArgs {
   int64_t h_base[MAX_LAYERS];  // chunk (16 B) offsets of h_l blocks
   int64_t d_base[MAX_LAYERS];  // chunk offsets of delta_l blocks
   int64_t a_base[MAX_LAYERS];  // chunk offsets of the Swish derivatives of h_l
+  // delta_L is not stashed (L >= 2): its weight gradient rebuilds it from dL/dz_o
+  // of every point (dob_base: 32 floats per 32-point block) and the last
+  // layer's ReLU mask words (m_base: one 16-byte chunk per lane and block) or
+  // its stashed Swish derivatives
+  int64_t dob_base, m_base;
   float* opart;              // [grid][H+1] output-layer gradient partials
   // fused mode
   const float* meas;         // [R] measured projections
@@ -116,6 +121,12 @@ struct WgArgs {
   int coords;                  // h blocks hold point coordinates (layer 1): the
                                // encoding is re-derived with Bmat
   const float4* Bmat;          // [FI/2] GRFF rows (t, z, y, x)
+  // the last layer (L >= 2): delta rebuilt as (w_o dL/dz_o) times the ReLU
+  // mask (dmode 1) or times the stashed Swish derivative (dmode 2, m_base =
+  // the layer's a_base); dmode 0: delta blocks at d_base
+  int dmode;
+  int64_t dob_base, m_base;
+  const float* wo;             // [H] w_o in unit order
   float* wpart;                // [splits][nh]
   int64_t split_base, nh;
   int64_t w_off, b_off;

@@ -297,6 +297,8 @@ __device__ inline void epi_chunk(const f32x16 (&acc)[Prec<PREC>::NB], int ob, in
 // sbias: this layer's biases in LDS (EPI_RELU, EPI_RELU_MASK).  gbias_next (or
 // none): biases of the next forward layer, copied into sbias_next.
 // stash (nullable): where to store x for the weight gradient.
+// drain_entry: wait for every outstanding memory operation before the first
+// panel (the layer before issued no stash stores after its last DMA).
 // Instruction stream per K-step: 2 MFMAs (one per point block), one LDS read
 // of the fragment D steps ahead, and a slice of the previous output block's
 // epilogue, so VALU work and LDS latency overlap the matrix cores.
@@ -308,7 +310,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
                              uint32_t (&msk)[mask_words<PREC, H>()],
                              typename Prec<PREC>::chunk_t* __restrict__ stash, char* sW0, char* sW1,
                              int lane, int w, int z,
-                             typename Prec<PREC>::chunk_t* __restrict__ actp = nullptr) {
+                             typename Prec<PREC>::chunk_t* __restrict__ actp = nullptr,
+                             bool drain_entry = false) {
   using T = Prec<PREC>;
   using chunk_t = typename T::chunk_t;
   constexpr int NB = T::NB, VPC = T::VPC;
@@ -340,7 +343,9 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
       // the panel DMA'd last is complete; stores issued after it may still drain
       // (a layer without a stash simply waits for everything outstanding)
       if (stash) {
-        if (pi == 0) wait_vm<VM_ENTRY>();
+        // drain_entry: the layer before stored nothing after its last DMA
+        if (pi == 0 && drain_entry) wait_vm<0>();
+        else if (pi == 0) wait_vm<VM_ENTRY>();
         else wait_vm<NB * SPP>();
       } else {
         wait_vm<0>();
@@ -661,6 +666,15 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         if (BWD_PART && ACT == 0 && l < L - 1)
 #pragma unroll
           for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+        if (BWD_PART && ACT == 0 && l == L - 1) {
+          // the last layer's mask words: its weight gradient rebuilds delta_L from
+          // them and dL/dz_o instead of reading it from the stash
+          static_assert(MSK_PER_LAYER <= 4, "one 16-byte chunk per lane");
+          u32x4 mw = {0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) mw[k] = mk[k];
+          __builtin_nontemporal_store(mw, (u32x4*)a.stash + a.m_base + blk0 * 64 + lane);
+        }
       };
       for (int l = 1; l < L; l += 2) {
         chunk_t t2[NB][CHh];
@@ -739,6 +753,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
                        WSrc after, int after_bytes) {
       const int64_t blk0 = blk_of(t);
       const float* wop = sWo + z + hf * (H / 2);
+      // dL/dz_o of every point: the last layer's weight gradient rebuilds
+      // delta_L from it (L >= 2: delta_L itself is not stashed)
+      if (L >= 2 && hf == 0)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          __builtin_nontemporal_store(
+              dob[nb], (float*)((chunk_t*)a.stash + a.dob_base) + (blk0 + nb) * 32 + pl);
       // delta_L = w_o dob . act'(z_L)
       chunk_t d[NB][CHh];
       if (ACT == 1) {
@@ -783,8 +804,9 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
             T::store_nt(&dstash(blk0, 0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
       }
       // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
-      // call stores its input delta_l for the weight gradient.  Two layers per
-      // iteration with swapped roles, as in the forward.
+      // call stores its input delta_l for the weight gradient (but delta_L,
+      // which the weight gradient rebuilds).  Two layers per iteration with
+      // swapped roles, as in the forward.
       auto adj = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
         uint32_t mk[MSK_PER_LAYER];
         if (ACT == 0)
@@ -796,8 +818,9 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         // entering from the forward's last layer or from the previous adjoint
         // layer: both stored their last panel's share of a width-H input
         layer<PREC, CHh, H, ADJ_EPI, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
-            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(blk0, l), sW0, sW1, lane, w, z,
-            astash(blk0, l - 1));
+            in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk,
+            l == L - 1 ? nullptr : dstash(blk0, l), sW0, sW1, lane, w, z, astash(blk0, l - 1),
+            l == L - 2);
       };
       for (int l = L - 1; l >= 1; l -= 2) {
         chunk_t t2[NB][CHh];
@@ -1140,6 +1163,15 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         if (BWD_PART && ACT == 0 && l < L - 1)
 #pragma unroll
           for (int k = 0; k < MSK_PER_LAYER; ++k) msk_w[(l * MSK_PER_LAYER + k) * 64 + lane] = mk[k];
+        if (BWD_PART && ACT == 0 && l == L - 1) {
+          // the last layer's mask words: its weight gradient rebuilds delta_L from
+          // them and dL/dz_o instead of reading it from the stash
+          static_assert(MSK_PER_LAYER <= 4, "one 16-byte chunk per lane");
+          u32x4 mw = {0u, 0u, 0u, 0u};
+#pragma unroll
+          for (int k = 0; k < MSK_PER_LAYER; ++k) mw[k] = mk[k];
+          __builtin_nontemporal_store(mw, (u32x4*)a.stash + a.m_base + blk0 * 64 + lane);
+        }
       };
       for (int l = 1; l < L; l += 2) {
         chunk_t t2[NB][CHh];
@@ -1296,6 +1328,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
           for (int o = 16; o > 0; o >>= 1) sb += __shfl_xor(sb, o);
           if (lane == 0) sdwo[w][H] += sb;
         }
+        // dL/dz_o of every point: the last layer's weight gradient rebuilds
+        // delta_L from it (L >= 2: delta_L itself is not stashed)
+        if (L >= 2 && hf == 0)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            __builtin_nontemporal_store(
+                dob[nb], (float*)((chunk_t*)a.stash + a.dob_base) + (blk0 + nb) * 32 + pl);
         // delta_L = w_o dob . act'(z_L)
         chunk_t d[NB][CHh];
         if (ACT == 1) {
@@ -1340,8 +1379,9 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
               T::store_nt(&dstash(0)[(nb * CHh + c) * 64 + lane], d[nb][c]);
         }
         // delta_{l-1} = (W_l^T delta_l) . relu'(z_{l-1}),  l = L .. 2; the layer
-        // call stores its input delta_l for the weight gradient.  Two layers per
-        // iteration with swapped roles, as in the forward.
+        // call stores its input delta_l for the weight gradient (but delta_L,
+        // which the weight gradient rebuilds).  Two layers per iteration with
+        // swapped roles, as in the forward.
         auto adj = [&](int l, const chunk_t (&in)[NB][CHh], chunk_t (&out)[NB][CHh]) {
           uint32_t mk[MSK_PER_LAYER];
           if (ACT == 0)
@@ -1353,8 +1393,8 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
           // entering from the forward's last layer or from the previous adjoint
           // layer: both stored their last panel's share of a width-H input
           layer<PREC, CHh, H, ADJ_EPI, NB * (CHh / (H / 32 / panel_obs<CHh, H>()))>(
-              in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk, dstash(l), sW0, sW1, lane, w, z,
-              astash(l - 1));
+              in, out, WTl(l), nx, nxb, nullptr, none, nullptr, mk,
+              l == L - 1 ? nullptr : dstash(l), sW0, sW1, lane, w, z, astash(l - 1), l == L - 2);
         };
         for (int l = L - 1; l >= 1; l -= 2) {
           chunk_t t2[NB][CHh];

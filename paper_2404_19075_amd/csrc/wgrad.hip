@@ -19,7 +19,12 @@ namespace dinr {
 template <int H>
 __host__ __device__ constexpr int wgrad_threads() { return H >= 256 ? 1024 : 512; }
 
-template <int PREC, int FI, int H, bool COORDS>
+// DM: 0 delta blocks from the stash; 1 the last layer's delta rebuilt from
+// dL/dz_o and the ReLU mask words; 2 from dL/dz_o and the Swish derivatives.
+// The last layer's delta is w_o[f] dL/dz_o act'(z_L)[f] (Eq. 5 through the
+// linear output): the transposition forms dL/dz_o act'(z_L) and the factor
+// w_o[f], common to row f of dW_L and to db_L[f], scales the finished rows.
+template <int PREC, int FI, int H, bool COORDS, int DM>
 __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   using T = Prec<PREC>;
   using E = typename T::elem_t;
@@ -49,6 +54,23 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   constexpr bool coords = COORDS;
   if (coords)
     for (int k = tid; k < FI / 2; k += blockDim.x) sBr[k] = a.Bmat[k];
+  // the table is read by other threads in the first transposition
+  __syncthreads();
+  // rebuilt delta: the mask bits of the register slots rho = VPC c + e of a
+  // thread's k-th chunk (q = tid + NTH k, c = (q / 64) mod CHd) sit at a place
+  // that does not depend on the iteration, so it is set once; when NTH / 64 is
+  // a multiple of CHd, c is the same for every k.  As the forward epilogue
+  // records them (output block ob = rho / 16 owns bits of word ob / 2): BF16
+  // word c / 4, bit 4 (c mod 4) + e / 2 + 16 (e mod 2); FP32 word c / 8, bit
+  // 16 ((c / 4) mod 2) + 4 (c mod 4) + e.
+  constexpr int NC = (NTH / 64) % CHd == 0 ? 1 : QD;
+  int m_word[NC], m_shift[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const int c = ((tid + NTH * k) / 64) % CHd;
+    m_word[k] = PREC == PREC_BF16 ? c / 4 : c / 8;
+    m_shift[k] = PREC == PREC_BF16 ? 4 * (c % 4) : 16 * ((c / 4) % 2) + 4 * (c % 4);
+  }
 
   const int64_t P = a.off[a.R];
   const int64_t n_tiles = (P + a.tile - 1) / a.tile;
@@ -83,7 +105,12 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
     for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
   float dbacc = 0.f, dbcomp = 0.f;  // bias gradient of the split, Kahan-summed
 
-  const chunk_t* __restrict__ Dst = (const chunk_t*)a.stash + a.d_base;
+  // delta blocks, or (rebuilt delta) the Swish derivative blocks / mask chunks
+  const chunk_t* __restrict__ Dst =
+      (const chunk_t*)a.stash + (DM == 2 ? a.m_base : DM == 1 ? a.m_base : a.d_base);
+  const float* __restrict__ Dob = (const float*)((const chunk_t*)a.stash + a.dob_base);
+  float dobv[DM ? QD : 1];
+  uint32_t mw[DM == 1 ? QD : 1];
   const chunk_t* __restrict__ Hst = (const chunk_t*)a.stash + a.h_base;
   const float4* __restrict__ Cst = (const float4*)a.stash + a.h_base;
   chunk_t cd[QD], ch[QH];
@@ -97,8 +124,17 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
 #pragma unroll
     for (int k = 0; k < QD; ++k) {
       const int q = tid + NTH * k;
-      const bool ok = it * NBLK + q / (CHd * 64) < nblk;
-      d[k] = ok ? *(const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+      const int64_t blk = it * NBLK + q / (CHd * 64);
+      const bool ok = blk < nblk;
+      if (DM == 1) {
+        // the word of lane q % 64's mask chunk that holds this thread's slots
+        // (shifted to bit 0), and the point's dL/dz_o
+        const int kc = NC == 1 ? 0 : k;
+        mw[k] = ok ? ((const uint32_t*)(Dst + blk * 64 + (q & 63)))[m_word[kc]] >> m_shift[kc] : 0u;
+      } else {
+        d[k] = ok ? *(const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+      }
+      if (DM) dobv[k] = ok ? Dob[blk * 32 + (q & 31)] : 0.f;
     }
     if (coords) {
       const int p = tid % BP;
@@ -124,7 +160,23 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
       const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
       const int p = bl * 32 + (l & 31);
 #pragma unroll
-      for (int e = 0; e < VPC; ++e) tD[feat(VPC * c + e, l >> 5) * ROW + p] = (E)T::get(cd[k], e);
+      for (int e = 0; e < VPC; ++e) {
+        const int f = feat(VPC * c + e, l >> 5);
+        if (DM == 0) {
+          tD[f * ROW + p] = (E)T::get(cd[k], e);
+        } else {
+          // delta_L / w_o = dL/dz_o . act'(z_L); the factor w_o of row f
+          // scales the finished row
+          float v;
+          if (DM == 2) {
+            v = dobv[k] * T::get(cd[k], e);
+          } else {
+            const int b = PREC == PREC_BF16 ? (e >> 1) + 16 * (e & 1) : e;
+            v = ((mw[k] >> b) & 1u) ? dobv[k] : 0.f;
+          }
+          tD[f * ROW + p] = (E)v;
+        }
+      }
     }
     if (coords) {
       // layer 1's input h_0 = [cos 2 pi u ; sin 2 pi u] re-derived exactly as
@@ -204,30 +256,43 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
-        out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] = acc[k][r];
+        out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] =
+            DM ? acc[k][r] * a.wo[row] : acc[k][r];
       }
     }
   }
-  if (tid < H) out[a.b_off + tid] = dbacc;
+  if (tid < H) out[a.b_off + tid] = DM ? dbacc * a.wo[tid] : dbacc;
 }
 
 #define DINR_SHAPES(X) X(128, 64) X(256, 256)
 
-template <int PREC, int FI, int H, bool COORDS>
+template <int PREC, int FI, int H, bool COORDS, int DM>
 static hipError_t wgrad_impl(const WgArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_wgrad<PREC, FI, H, COORDS>), dim3(grid), dim3(wgrad_threads<H>()), 0, st,
-                     a);
+  hipLaunchKernelGGL((k_wgrad<PREC, FI, H, COORDS, DM>), dim3(grid), dim3(wgrad_threads<H>()), 0,
+                     st, a);
   return hipGetLastError();
 }
 
+template <int PREC, int FI, int H>
+static hipError_t wgrad_hidden(const WgArgs& a, int grid, hipStream_t st) {
+  switch (a.dmode) {
+    case 0: return wgrad_impl<PREC, FI, H, false, 0>(a, grid, st);
+    case 1: return wgrad_impl<PREC, FI, H, false, 1>(a, grid, st);
+    case 2: return wgrad_impl<PREC, FI, H, false, 2>(a, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Layer 1 (coordinates) always reads stashed delta blocks: its delta is the
+// last layer's only when L = 1, and then it is stashed.
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
 #define X(I, HH)                                                                  \
-  if (h == HH && fi == I && a.coords)                                             \
-    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH, true>(a, grid, st)    \
-                             : wgrad_impl<PREC_F32, I, HH, true>(a, grid, st);    \
+  if (h == HH && fi == I && a.coords && a.dmode == 0)                             \
+    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH, true, 0>(a, grid, st) \
+                             : wgrad_impl<PREC_F32, I, HH, true, 0>(a, grid, st); \
   if (h == HH && fi == HH && !a.coords)                                           \
-    return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, HH, HH, false>(a, grid, st)  \
-                             : wgrad_impl<PREC_F32, HH, HH, false>(a, grid, st);
+    return prec == PREC_BF16 ? wgrad_hidden<PREC_BF16, HH, HH>(a, grid, st)       \
+                             : wgrad_hidden<PREC_F32, HH, HH>(a, grid, st);
   DINR_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
