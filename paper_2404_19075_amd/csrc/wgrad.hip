@@ -159,22 +159,44 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
       const int q = tid + NTH * k;
       const int bl = q / (CHd * 64), c = (q / 64) % CHd, l = q & 63;
       const int p = bl * 32 + (l & 31);
+      // rebuilt delta: delta_L / w_o = dL/dz_o . act'(z_L); the factor w_o of
+      // row f scales the finished row.  ReLU: the element is dL/dz_o where
+      // the mask bit is set, else 0.  In BF16 the bits of slots 2j and 2j + 1
+      // are bits j and j + 16 of the word, so (word >> j) & 0x10001 times the
+      // 16 bits of dL/dz_o is the packed pair (one 24-bit multiply).
+      if constexpr (DM == 1 && PREC == PREC_BF16) {
+        const uint32_t dbits = __builtin_bit_cast(uint16_t, (E)dobv[k]);
+#pragma unroll
+        for (int j = 0; j < VPC / 2; ++j) {
+          const uint32_t pr = ((mw[k] >> j) & 0x10001u) * dbits;
+          tD[feat(VPC * c + 2 * j, l >> 5) * ROW + p] = __builtin_bit_cast(E, (uint16_t)pr);
+          tD[feat(VPC * c + 2 * j + 1, l >> 5) * ROW + p] =
+              __builtin_bit_cast(E, (uint16_t)(pr >> 16));
+        }
+        continue;
+      }
+      // Swish, BF16: the pair 2j, 2j + 1 is rounded by one packed conversion
+      if constexpr (DM == 2 && PREC == PREC_BF16) {
+        typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+        typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+#pragma unroll
+        for (int j = 0; j < VPC / 2; ++j) {
+          const f32x2_t v = {dobv[k] * T::get(cd[k], 2 * j), dobv[k] * T::get(cd[k], 2 * j + 1)};
+          const bf16x2_t r = __builtin_convertvector(v, bf16x2_t);
+          tD[feat(VPC * c + 2 * j, l >> 5) * ROW + p] = r[0];
+          tD[feat(VPC * c + 2 * j + 1, l >> 5) * ROW + p] = r[1];
+        }
+        continue;
+      }
 #pragma unroll
       for (int e = 0; e < VPC; ++e) {
         const int f = feat(VPC * c + e, l >> 5);
         if (DM == 0) {
           tD[f * ROW + p] = (E)T::get(cd[k], e);
+        } else if (DM == 2) {
+          tD[f * ROW + p] = (E)(dobv[k] * T::get(cd[k], e));
         } else {
-          // delta_L / w_o = dL/dz_o . act'(z_L); the factor w_o of row f
-          // scales the finished row
-          float v;
-          if (DM == 2) {
-            v = dobv[k] * T::get(cd[k], e);
-          } else {
-            const int b = PREC == PREC_BF16 ? (e >> 1) + 16 * (e & 1) : e;
-            v = ((mw[k] >> b) & 1u) ? dobv[k] : 0.f;
-          }
-          tD[f * ROW + p] = (E)v;
+          tD[f * ROW + p] = ((mw[k] >> e) & 1u) ? (E)dobv[k] : (E)0.f;
         }
       }
     }
