@@ -196,7 +196,7 @@ def serving(batch, params_np, n_req=1000, rates=(0.1, 0.5, 1.0, 2.0), n_cap=200,
 
 
 KERNEL_SOURCES = ["dinr_dev.h", "ray_dev.h", "kernels.h", "mlp.h", "mlp_inst.hip", "wgrad.hip",
-                  "kernels.hip"]
+                  "kernels.hip", "dinr_api.hip"]
 
 
 def kernel_source_digest():

@@ -57,7 +57,7 @@ struct Plan {
   void* stash = nullptr;
   int64_t chunk_points = 0, n_chunks = 0, kb = 0, splits_per_chunk = 0;
   int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS], a_base[MAX_LAYERS];
-  int64_t dob_base = 0, m_base = 0;
+  int64_t dob_base = 0, m_base = 0, ring_blocks = 0;
   float* wpart = nullptr;
   float* opart = nullptr;
   double* lpart = nullptr;
@@ -161,14 +161,24 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   // bytes), h_1 .. h_{L-1} and delta_1 .. delta_{L-1}; delta_L (L >= 2) as
   // dL/dz_o (4 bytes) and, ReLU, the last layer's mask bits (32 bytes per
   // point at H = 256, one 16-byte chunk per lane and 32-point block); Swish: the
-  // activation derivative of every hidden output as well
+  // last layer's activation derivatives as well.  The Swish derivatives of the
+  // other layers are read only by the adjoint of the same tile: they live in a
+  // ring per workgroup of the persistent kernel, one tile deep (the group of
+  // tiles of one projection in the grouped one-pass step).
   const int64_t hb = (int64_t)c->H * esize(c->prec);
   const bool compact = c->L >= 2;
+  const bool swish = c->mlp.act == DINR_SWISH;
   int64_t per_point = 16;
   for (int l = 1; l < c->L; ++l) per_point += hb;
   per_point += (int64_t)(compact ? c->L - 1 : c->L) * hb;
-  if (compact) per_point += 4 + (c->mlp.act == DINR_SWISH ? 0 : 32);
-  if (c->mlp.act == DINR_SWISH) per_point += (int64_t)c->L * hb;
+  if (compact) per_point += 4 + (swish ? 0 : 32);
+  if (swish) per_point += hb;
+  const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
+  const int64_t layer_chunks = (int64_t)(c->H / vpc2) * 64;  // per 32-point block and layer
+  const int64_t group = c->samp.mode == 0 ? p->D2 * c->samp.n / c->tile : 0;
+  p->ring_blocks = (group >= 2 && group <= 64 ? group : 1) * (c->tile / 32);
+  const int64_t ring_chunks = swish ? (int64_t)(c->L - 1) * p->grid_mlp * p->ring_blocks *
+                                          layer_chunks : 0;
   const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
   const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
   const int64_t total_splits = pts_pad / k_split;
@@ -184,7 +194,7 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
     const int64_t n_chunks = (pts_pad + chunk - 1) / chunk;
     p->opart = A.take<float>((size_t)n_chunks * p->grid_mlp * (c->H + 1));
     p->lpart = A.take<double>((size_t)n_chunks * p->grid_mlp);
-    p->stash = A.take<char>((size_t)chunk * per_point);
+    p->stash = A.take<char>((size_t)ring_chunks * 16 + (size_t)chunk * per_point);
     if (A.ok) {
       p->chunk_points = chunk;
       p->n_chunks = n_chunks;
@@ -202,21 +212,21 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
     ks *= 2;
   p->kb = ks / 32;
   p->splits_per_chunk = p->chunk_points / ks;
-  // stash region of each layer: h blocks then delta blocks, in 16-byte chunks
-  int64_t base = 0;
-  const int vpc2 = (c->prec == DINR_BF16 ? 8 : 4) * 2;  // features per 16-byte lane pair
+  // the Swish derivative ring (layers 1 .. L-1), then the stash region of each
+  // layer: h blocks then delta blocks, in 16-byte chunks
+  for (int l = 0; l + 1 < c->L; ++l)
+    p->a_base[l] = swish ? (int64_t)l * p->grid_mlp * p->ring_blocks * layer_chunks : 0;
+  int64_t base = ring_chunks;
   const int64_t blocks = p->chunk_points / 32;
   for (int l = 0; l < c->L; ++l) {
     p->h_base[l] = base;
     // layer 1: one 16-byte chunk of coordinates per point
-    base += l == 0 ? p->chunk_points : blocks * (c->H / vpc2) * 64;
+    base += l == 0 ? p->chunk_points : blocks * layer_chunks;
     p->d_base[l] = base;
-    if (!(compact && l == c->L - 1)) base += blocks * (c->H / vpc2) * 64;
+    if (!(compact && l == c->L - 1)) base += blocks * layer_chunks;
   }
-  for (int l = 0; l < c->L; ++l) {
-    p->a_base[l] = base;
-    if (c->mlp.act == DINR_SWISH) base += blocks * (c->H / vpc2) * 64;
-  }
+  p->a_base[c->L - 1] = base;
+  if (swish) base += blocks * layer_chunks;
   // delta_L's substitutes: 32 floats (8 chunks) of dL/dz_o and, ReLU, 64 mask
   // chunks per block
   p->dob_base = base;
@@ -319,6 +329,7 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       a.d_base[l] = p.d_base[l];
       a.a_base[l] = p.a_base[l];
     }
+    a.ring_blocks = p.ring_blocks;
     a.dob_base = p.dob_base;
     a.m_base = p.m_base;
     a.opart = p.opart + ch * (int64_t)p.grid_mlp * (c->H + 1);

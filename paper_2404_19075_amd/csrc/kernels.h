@@ -93,7 +93,12 @@ struct MlpArgs {
   void* stash;
   int64_t h_base[MAX_LAYERS];  // chunk (16 B) offsets of h_l blocks
   int64_t d_base[MAX_LAYERS];  // chunk offsets of delta_l blocks
-  int64_t a_base[MAX_LAYERS];  // chunk offsets of the Swish derivatives of h_l
+  // chunk offsets of the Swish derivatives of h_l: the last layer's per point
+  // (its weight gradient reads them); the other layers' in a ring of
+  // ring_blocks 32-point blocks per workgroup, rewritten by every tile (group)
+  // the workgroup takes, since only that tile's adjoint reads them
+  int64_t a_base[MAX_LAYERS];
+  int64_t ring_blocks;
   // delta_L is not stashed (L >= 2): its weight gradient rebuilds it from dL/dz_o
   // of every point (dob_base: 32 floats per 32-point block) and the last
   // layer's ReLU mask words (m_base: one 16-byte chunk per lane and block) or

@@ -515,10 +515,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
   if constexpr (GROUP) {
     // ---- stash addresses of a tile: its first 32-point block for this wave
     auto blk_of = [&](int64_t t) -> int64_t { return (t - a.tile_begin) * (TILE / 32) + w * NB; };
-    // Swish derivatives of layer l's outputs, in the layout of the stash
+    // Swish derivatives of layer l's outputs, in the layout of the stash: the
+    // last layer's per point, the others' in the workgroup's ring (one group)
     auto astash = [&](int64_t blk0, int l) -> chunk_t* {
-      return (BWD_PART && ACT == 1) ? (chunk_t*)a.stash + a.a_base[l] + blk0 * (CHh * 64)
-                                    : nullptr;
+      if (!(BWD_PART && ACT == 1)) return nullptr;
+      const int64_t rb = l + 1 < L ? (int64_t)blockIdx.x * a.ring_blocks + blk0 % a.ring_blocks
+                                   : blk0;
+      return (chunk_t*)a.stash + a.a_base[l] + rb * (CHh * 64);
     };
     auto hstash = [&](int64_t blk0, int l, int ch) -> chunk_t* {
       return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
@@ -1115,10 +1118,13 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         }
       }
       uint32_t* msk_w = &smsk[w][0][0][0];
-      // Swish derivatives of layer l's outputs, in the layout of the stash
+      // Swish derivatives of layer l's outputs, in the layout of the stash: the
+      // last layer's per point, the others' in the workgroup's ring (one tile)
       auto astash = [&](int l) -> chunk_t* {
-        return (BWD_PART && ACT == 1) ? (chunk_t*)a.stash + a.a_base[l] + blk0 * (CHh * 64)
-                                      : nullptr;
+        if (!(BWD_PART && ACT == 1)) return nullptr;
+        const int64_t rb =
+            l + 1 < L ? (int64_t)blockIdx.x * a.ring_blocks + blk0 % a.ring_blocks : blk0;
+        return (chunk_t*)a.stash + a.a_base[l] + rb * (CHh * 64);
       };
       auto hstash = [&](int l, int ch) -> chunk_t* {
         return BWD_PART ? (chunk_t*)a.stash + a.h_base[l] + blk0 * (ch * 64) : nullptr;
