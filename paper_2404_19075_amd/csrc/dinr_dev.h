@@ -60,6 +60,10 @@ struct Prec<PREC_BF16> {
   __device__ static inline void store_nt(chunk_t* p, const chunk_t& v) {
     __builtin_nontemporal_store(v, p);
   }
+  // streaming load (data read once: kept from displacing reused data in L2)
+  __device__ static inline chunk_t load_nt(const chunk_t* p) {
+    return __builtin_nontemporal_load(p);
+  }
 };
 
 template <>
@@ -86,6 +90,11 @@ struct Prec<PREC_F32> {
     typedef float f4 __attribute__((ext_vector_type(4)));
     const f4 t = {v.x, v.y, v.z, v.w};
     __builtin_nontemporal_store(t, (f4*)p);
+  }
+  __device__ static inline chunk_t load_nt(const chunk_t* p) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 t = __builtin_nontemporal_load((const f4*)p);
+    return make_float4(t.x, t.y, t.z, t.w);
   }
 };
 

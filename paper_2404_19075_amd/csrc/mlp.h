@@ -333,7 +333,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
     for (int k = 0; k < mask_words<PREC, H>(); ++k) msk[k] = 0u;
   f32x16 accp[NB];
   // EPI_DERIV: derivative chunk k of an output block, loaded at the K-step
-  // where chunk k of the block before is consumed (one block of latency)
+  // where chunk k of the block before is consumed (one block of latency);
+  // streaming loads, so that the weight panels stay in L2
   chunk_t actk[NEPI];
   const char* ap = (const char*)actp + lane_off((uint32_t)(lane * sizeof(chunk_t)));
 #pragma unroll
@@ -412,8 +413,8 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
 #pragma unroll
         for (int k = 0; k < NEPI; ++k)
           if ((k * KC) / NEPI == c)
-            actk[k] = *(const chunk_t*)(ap + ((k / CPO) * chunks<PREC>(H) + ob * CPO + k % CPO) *
-                                                 64 * sizeof(chunk_t));
+            actk[k] = T::load_nt((const chunk_t*)(ap + ((k / CPO) * chunks<PREC>(H) + ob * CPO +
+                                                        k % CPO) * 64 * sizeof(chunk_t)));
       }
     }
 #pragma unroll
@@ -774,7 +775,8 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
           for (int c = 0; c < CHh; ++c)
-            d[nb][c] = *(const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t));
+            d[nb][c] =
+                T::load_nt((const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t)));
       }
 #pragma unroll
       for (int c = 0; c < CHh; ++c) {
@@ -1351,7 +1353,8 @@ __global__ __launch_bounds__(Prec<PREC>::WAVES * 64, 1) void k_mlp(MlpArgs a) {
           for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int c = 0; c < CHh; ++c)
-              d[nb][c] = *(const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t));
+              d[nb][c] =
+                T::load_nt((const chunk_t*)(ap + (nb * CHh + c) * 64 * sizeof(chunk_t)));
         }
 #pragma unroll
         for (int c = 0; c < CHh; ++c) {
