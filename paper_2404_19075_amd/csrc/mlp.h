@@ -327,6 +327,11 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
   static_assert(OB % OBP == 0, "panels must tile the output blocks");
   static_assert(KC % NP == 0, "stash stores must spread evenly over the panels");
   static_assert(NP % 2 == 0, "each layer starts and ends in buffer 0");
+  // BF16 ReLU layers issue the panel's stash stores spread over the K-steps of
+  // its first block (2 % faster than a burst after the barrier); the Swish
+  // layers, whose epilogues also store and load derivatives, keep the burst
+  // (spreading there is 12 % slower), and so does FP32 (spreading makes it spill)
+  constexpr bool SPREAD = PREC == PREC_BF16 && (EPI == EPI_RELU_MASK || EPI == EPI_MASK);
   const int hf = lane >> 5;
   if (EPI == EPI_RELU_MASK)
 #pragma unroll
@@ -359,7 +364,7 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
       if (ob + OBP < OB) dma_panel<T::WAVES>(W.at((pi + 1) * PB), nxt, PB, w, lane);
       else if (Wnext.off >= 0) dma_panel<T::WAVES>(Wnext, nxt, next_bytes, w, lane);
       asm volatile("" ::: "memory");  // the stores below stay after the DMA
-      if (stash) {
+      if (stash && !SPREAD) {
         // this panel's share of the layer input for the weight gradient
         char* sp = (char*)stash + lane_off((uint32_t)(lane * sizeof(chunk_t)));
 #pragma unroll
@@ -402,6 +407,14 @@ __device__ inline void layer(const typename Prec<PREC>::chunk_t (&x)[Prec<PREC>:
       for (int nb = 0; nb < NB; ++nb) T::mma(acc[nb], a[c % (D + 1)], x[nb][c]);
       __builtin_amdgcn_sched_group_barrier(0x008, MFMA_PER_STEP, 0);
       if (c + D < KC) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      if (SPREAD && stash && ob % OBP == 0 && c % (KC / SPP) == 0) {
+        // the panel's stash stores, one every KC / SPP K-steps of its first block
+        const int cs = (ob / OBP) * SPP + c / (KC / SPP);
+        char* sp = (char*)stash + lane_off((uint32_t)(lane * sizeof(chunk_t)));
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          T::store_nt((chunk_t*)(sp + (nb * KC + cs) * 64 * sizeof(chunk_t)), x[nb][cs]);
+      }
       if (ob > 0) {
         // epilogue chunks of block ob-1 assigned to this step
 #pragma unroll
