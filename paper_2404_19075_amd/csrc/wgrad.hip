@@ -286,6 +286,187 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   if (tid < H) out[a.b_off + tid] = DM ? dbacc * a.wo[tid] : dbacc;
 }
 
+// dW_l and db_l of a hidden BF16 layer of width 256 whose delta blocks are
+// stashed (the layers between the first and the last): the same reduction as
+// k_wgrad, with the stash streamed by DMA straight into an LDS ring of four
+// 32-point blocks (16 KB of delta and 16 KB of h each), three blocks ahead of
+// the one being reduced, and the matrix-core operands read out of the ring
+// with transposing loads (ds_read_b64_tr_b16) instead of being transposed
+// element by element through registers.  Within a 16-lane group that load
+// hands lane 4q + i element i of the 8-byte reads of lanes q, q + 4, q + 8,
+// q + 12; a stash chunk's elements 4j .. 4j + 3 are four consecutive features
+// of one point (feat()), so lanes q + 4e reading points p0 + e of the same
+// four features give lane 4q + i feature i of them at four consecutive points:
+// a quarter of its operand (rows = features, K = points).  Two such loads
+// make the eight points of a 32x32x16 operand.  The ring keeps the chunk
+// layout of the stash except that the upper half of each chunk (lanes 32-63)
+// is stored at point index p xor 4, so that a group's eight 16-byte pieces
+// fall in distinct LDS banks.
+constexpr int WTR_THREADS = 1024;
+
+__device__ inline bf16x8 tr_pair(const char* a0, const char* a1) {
+  typedef short v4i16 __attribute__((ext_vector_type(4)));
+  typedef short v8i16 __attribute__((ext_vector_type(8)));
+  const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) v4i16*)(const_cast<char*>(a0)));
+  const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+      (__attribute__((address_space(3))) v4i16*)(const_cast<char*>(a1)));
+  const v8i16 v = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+__global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
+  constexpr int H = 256, FI = 256, CH = H / 16;  // 16-byte chunks per lane and block
+  constexpr int NW = WTR_THREADS / 64;           // 16 waves: wave w moves chunk w
+  static_assert(NW == CH, "one delta and one h chunk per wave and block");
+  constexpr int HALF = CH * 1024;                // delta (or h) bytes of one block
+  __shared__ __align__(16) char ring0[2 * HALF];
+  __shared__ __align__(16) char ring1[2 * HALF];
+  __shared__ __align__(16) char ring2[2 * HALF];
+  __shared__ __align__(16) char ring3[2 * HALF];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+
+  const int64_t P = a.off[a.R];
+  const int64_t n_tiles = (P + a.tile - 1) / a.tile;
+  int64_t pend = n_tiles * a.tile;
+  if (pend > a.chunk_p1) pend = a.chunk_p1;
+  const int64_t nblk = (pend - a.chunk_p0) / 32;  // valid 32-point blocks of the chunk
+  // the split's blocks, as k_wgrad takes them (pairs of blocks; a pair that
+  // straddles the end of the chunk reads zeros for its second block)
+  const int64_t b0 = (int64_t)blockIdx.x * a.kb;
+  const int64_t nb2 = (nblk + 1) / 2 * 2;
+  if (b0 >= nb2) return;
+  const int64_t b1 = b0 + a.kb < nb2 ? b0 + a.kb : nb2;
+
+  // DMA of block b into a ring slot: wave w copies delta chunk w and h chunk
+  // w; lane l's 16 bytes are the stash piece pi(l) of that chunk (pi: the
+  // upper half at point xor 4, an involution).  Blocks past the chunk's end
+  // get an empty buffer range: the copy writes zeros.
+  const int piece = lane < 32 ? lane : 32 + ((lane - 32) ^ 4);
+  const uint32_t voff = lane_off((uint32_t)((w * 64 + piece) * 16));
+  const char* stash = (const char*)a.stash;
+  auto dma = [&](int64_t b, char* slot) {
+    const bool ok = b < nblk;
+    const char* d = stash + (a.d_base + b * CH * 64) * 16;
+    const char* h = stash + (a.h_base + b * CH * 64) * 16;
+    const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(d, ok ? HALF : 0);
+    const __amdgpu_buffer_rsrc_t rh = buffer_rsrc(h, ok ? HALF : 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void*)(slot + w * 1024), 16, (int)voff, 0,
+                                             0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rh, (lds_void*)(slot + HALF + w * 1024), 16,
+                                             (int)voff, 0, 0, 0);
+  };
+
+  // operand addresses: wave w holds tiles (rb, cb) for rb in {2 (w / 4), +1},
+  // cb in {2 (w % 4), +1}.  Lane l as a source of the transposing load: group
+  // g = l / 16, s = l % 16, point offset e = s / 4, quad q = s % 4; rows
+  // 16 (g % 2) + 4 q .. + 3 of the tile are features of chunk 2 rb + g % 2,
+  // half q % 2, elements 4 (q / 2) .. + 3; points 8 (g / 2) + e (+ 4 for the
+  // second load, + 16 for the second K-step)
+  const int g = lane >> 4, e = (lane >> 2) & 3, q = lane & 3;
+  const int hfq = q & 1, pl = 8 * (g >> 1) + e;
+  // piece of point pl (first load) and pl + 4 (second), upper half at xor 4
+  const int pc0 = hfq ? 32 + (pl ^ 4) : pl;
+  const int pc1 = hfq ? 32 + ((pl + 4) ^ 4) : pl + 4;
+  const int lane_b0 = pc0 * 16 + 8 * (q >> 1), lane_b1 = pc1 * 16 + 8 * (q >> 1);
+  const int rb0 = 2 * (w / 4), cb0 = 2 * (w % 4);
+  // byte offsets inside a slot of the rows this lane sources for the first
+  // row (column) block of the wave; the second block is two chunks (2 KB)
+  // further, the second K-step 16 points (256 B) further
+  const int oa0 = (int)lane_off((uint32_t)((2 * rb0 + (g & 1)) * 1024 + lane_b0));
+  const int oa1 = (int)lane_off((uint32_t)((2 * rb0 + (g & 1)) * 1024 + lane_b1));
+  const int ob0 = (int)lane_off((uint32_t)(HALF + (2 * cb0 + (g & 1)) * 1024 + lane_b0));
+  const int ob1 = (int)lane_off((uint32_t)(HALF + (2 * cb0 + (g & 1)) * 1024 + lane_b1));
+  // bias gradient: the waves with w % 4 = 0 hold the delta fragments of every
+  // row block; lane l sums its eight points of feature 32 rb + l % 32 for each
+  // K-step, Kahan-accumulates the block's sum, and the two K halves (lanes l
+  // and l + 32) are added at the end
+  const bool db_wave = (w & 3) == 0;
+  f32x16 acc[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+  float dbacc[2] = {0.f, 0.f}, dbcomp[2] = {0.f, 0.f};
+
+  auto step = [&](int64_t b, char* cur, char* nxt) {
+    // this wave's copies of block b are done (those of b + 1 and b + 2, two
+    // instructions each, may still run); the barrier makes every wave's
+    // copies visible and frees the slot block b - 1 was reduced from
+    wait_vm<4>();
+    panel_barrier();
+    dma(b + 3, nxt);
+    float sbk[2] = {0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      bf16x8 fa[2], fh[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        fa[k] = tr_pair(cur + oa0 + 2048 * k + 256 * st, cur + oa1 + 2048 * k + 256 * st);
+        fh[k] = tr_pair(cur + ob0 + 2048 * k + 256 * st, cur + ob1 + 2048 * k + 256 * st);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[k >> 1], fh[k & 1], acc[k], 0, 0, 0);
+      if (db_wave) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          float sb = 0.f;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) sb += (float)fa[k][i];
+          sbk[k] += sb;
+        }
+      }
+    }
+    if (db_wave) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const float y = sbk[k] - dbcomp[k];
+        const float t = dbacc[k] + y;
+        dbcomp[k] = (t - dbacc[k]) - y;
+        dbacc[k] = t;
+      }
+    }
+  };
+  dma(b0, ring0);
+  dma(b0 + 1, ring1);
+  dma(b0 + 2, ring2);
+  // the split's block count is even (kb even; the last split ends at an even
+  // block): the ring turns in steps of four with a tail of two
+  for (int64_t b = b0; b < b1; b += 4) {
+    step(b, ring0, ring3);
+    step(b + 1, ring1, ring0);
+    if (b + 2 < b1) {
+      step(b + 2, ring2, ring1);
+      step(b + 3, ring3, ring2);
+    }
+  }
+  // drain the copies issued past the split's end before the workgroup exits
+  wait_vm<0>();
+
+  float* out = a.wpart + (a.split_base + blockIdx.x) * a.nh;
+  const int hf = lane >> 5;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int rb = rb0 + (k >> 1), cb = cb0 + (k & 1);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
+      out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] = acc[k][r];
+    }
+  }
+  if (db_wave) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      // the upper half's points of the same feature (lane + 32), compensation
+      // included
+      const float own = dbacc[k] - dbcomp[k];
+      const float other = __shfl_xor(own, 32);
+      if (lane < 32) out[a.b_off + 32 * (rb0 + k) + lane] = own + other;
+    }
+  }
+}
+
 #define DINR_SHAPES(X) X(128, 64) X(256, 256)
 
 template <int PREC, int FI, int H, bool COORDS, int DM>
@@ -308,6 +489,10 @@ static hipError_t wgrad_hidden(const WgArgs& a, int grid, hipStream_t st) {
 // Layer 1 (coordinates) always reads stashed delta blocks: its delta is the
 // last layer's only when L = 1, and then it is stashed.
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
+  if (prec == PREC_BF16 && fi == 256 && h == 256 && !a.coords && a.dmode == 0) {
+    hipLaunchKernelGGL(k_wgrad_tr, dim3(grid), dim3(WTR_THREADS), 0, st, a);
+    return hipGetLastError();
+  }
 #define X(I, HH)                                                                  \
   if (h == HH && fi == I && a.coords && a.dmode == 0)                             \
     return prec == PREC_BF16 ? wgrad_impl<PREC_BF16, I, HH, true, 0>(a, grid, st) \
