@@ -130,11 +130,13 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
         // the word of lane q % 64's mask chunk that holds this thread's slots
         // (shifted to bit 0), and the point's dL/dz_o
         const int kc = NC == 1 ? 0 : k;
-        mw[k] = ok ? ((const uint32_t*)(Dst + blk * 64 + (q & 63)))[m_word[kc]] >> m_shift[kc] : 0u;
+        mw[k] = ok ? __builtin_nontemporal_load((const uint32_t*)(Dst + blk * 64 + (q & 63)) +
+                                                m_word[kc]) >> m_shift[kc]
+                   : 0u;
       } else {
-        d[k] = ok ? *(const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+        d[k] = ok ? T::load_nt((const chunk_t*)(db + toff + NTH * k * sizeof(chunk_t))) : T::zero();
       }
-      if (DM) dobv[k] = ok ? Dob[blk * 32 + (q & 31)] : 0.f;
+      if (DM) dobv[k] = ok ? __builtin_nontemporal_load(Dob + blk * 32 + (q & 31)) : 0.f;
     }
     if (coords) {
       const int p = tid % BP;
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
     for (int k = 0; k < QH; ++k) {
       const int q = tid + NTH * k;
       const bool ok = it * NBLK + q / (CHi * 64) < nblk;
-      h[k] = ok ? *(const chunk_t*)(hb + toff + NTH * k * sizeof(chunk_t)) : T::zero();
+      h[k] = ok ? T::load_nt((const chunk_t*)(hb + toff + NTH * k * sizeof(chunk_t))) : T::zero();
     }
   };
   // Transposition of the registers' iteration into one LDS buffer pair, and
@@ -351,10 +353,11 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
     const char* h = stash + (a.h_base + b * CH * 64) * 16;
     const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(d, ok ? HALF : 0);
     const __amdgpu_buffer_rsrc_t rh = buffer_rsrc(h, ok ? HALF : 0);
+    // cache policy 2: streaming (nt), the stash is read once
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void*)(slot + w * 1024), 16, (int)voff, 0,
-                                             0, 0);
+                                             0, 2);
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rh, (lds_void*)(slot + HALF + w * 1024), 16,
-                                             (int)voff, 0, 0, 0);
+                                             (int)voff, 0, 0, 2);
   };
 
   // operand addresses: wave w holds tiles (rb, cb) for rb in {2 (w / 4), +1},
