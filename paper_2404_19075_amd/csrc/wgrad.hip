@@ -288,22 +288,27 @@ __global__ __launch_bounds__(wgrad_threads<H>()) void k_wgrad(WgArgs a) {
   if (tid < H) out[a.b_off + tid] = DM ? dbacc * a.wo[tid] : dbacc;
 }
 
-// dW_l and db_l of a hidden BF16 layer of width 256 whose delta blocks are
-// stashed (the layers between the first and the last): the same reduction as
-// k_wgrad, with the stash streamed by DMA straight into an LDS ring of four
-// 32-point blocks (16 KB of delta and 16 KB of h each), three blocks ahead of
-// the one being reduced, and the matrix-core operands read out of the ring
-// with transposing loads (ds_read_b64_tr_b16) instead of being transposed
-// element by element through registers.  Within a 16-lane group that load
-// hands lane 4q + i element i of the 8-byte reads of lanes q, q + 4, q + 8,
-// q + 12; a stash chunk's elements 4j .. 4j + 3 are four consecutive features
-// of one point (feat()), so lanes q + 4e reading points p0 + e of the same
-// four features give lane 4q + i feature i of them at four consecutive points:
-// a quarter of its operand (rows = features, K = points).  Two such loads
-// make the eight points of a 32x32x16 operand.  The ring keeps the chunk
-// layout of the stash except that the upper half of each chunk (lanes 32-63)
-// is stored at point index p xor 4, so that a group's eight 16-byte pieces
-// fall in distinct LDS banks.
+// dW_l and db_l of a BF16 layer of width 256 (fan-in 256): the same reduction
+// as k_wgrad, with the stash streamed by DMA straight into an LDS ring of
+// four 32-point blocks and the matrix-core operands read out of the ring with
+// transposing loads (ds_read_b64_tr_b16) instead of being transposed element
+// by element through registers.  Within a 16-lane group that load hands lane
+// 4q + i element i of the 8-byte reads of lanes q, q + 4, q + 8, q + 12; a
+// stash chunk's elements 4j .. 4j + 3 are four consecutive features of one
+// point (feat()), so lanes q + 4e reading points p0 + e of the same four
+// features give lane 4q + i feature i of them at four consecutive points: a
+// quarter of its operand (rows = features, K = points).  Two such loads make
+// the eight points of a 32x32x16 operand.  The ring keeps the chunk layout of
+// the stash except that the upper half of each chunk (lanes 32-63) is stored
+// at point index p xor 4, so that a group's eight 16-byte pieces fall in
+// distinct LDS banks.
+// DM 0: delta blocks copied from the stash (three blocks ahead).  DM 1 / 2:
+// the last layer's delta / w_o = dL/dz_o . act'(z_L), built in the ring from
+// the copied ReLU mask words or Swish derivatives and dL/dz_o, and w_o[f]
+// scales the finished rows.  COORDS: h_0 is the Fourier encoding of the
+// copied coordinates (App. B item 2), built in the ring through the forward's
+// phase and sin/cos functions.  Blocks that are built are built one step
+// ahead of their reduction (copies two blocks ahead).
 constexpr int WTR_THREADS = 1024;
 
 __device__ inline bf16x8 tr_pair(const char* a0, const char* a1) {
@@ -317,16 +322,47 @@ __device__ inline bf16x8 tr_pair(const char* a0, const char* a1) {
   return __builtin_bit_cast(bf16x8, v);
 }
 
+// Wait until at most n vector-memory operations are outstanding (n < 16).
+__device__ inline void wait_vm_n(int n) {
+  switch (n) {
+    case 0: wait_vm<0>(); break;
+    case 1: wait_vm<1>(); break;
+    case 2: wait_vm<2>(); break;
+    case 3: wait_vm<3>(); break;
+    case 4: wait_vm<4>(); break;
+    case 5: wait_vm<5>(); break;
+    default: wait_vm<6>(); break;
+  }
+}
+
+template <int DM, bool COORDS>
 __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   constexpr int H = 256, FI = 256, CH = H / 16;  // 16-byte chunks per lane and block
   constexpr int NW = WTR_THREADS / 64;           // 16 waves: wave w moves chunk w
   static_assert(NW == CH, "one delta and one h chunk per wave and block");
+  static_assert(!(COORDS && DM != 0), "layer 1's delta is stashed");
+  constexpr bool BUILD = DM != 0 || COORDS;
   constexpr int HALF = CH * 1024;                // delta (or h) bytes of one block
-  __shared__ __align__(16) char ring0[2 * HALF];
-  __shared__ __align__(16) char ring1[2 * HALF];
-  __shared__ __align__(16) char ring2[2 * HALF];
-  __shared__ __align__(16) char ring3[2 * HALF];
+  constexpr int AUX = 2 * HALF;                  // mask words or coordinates (1 KB), dL/dz_o
+  // COORDS: a copy of the GRFF rows in every slot, never a copy target.  (Kept
+  // in an array of its own, the rows' reads would wait for every copy in
+  // flight: the compiler cannot tell that array from the copies' targets.)
+  constexpr int BROWS = AUX + 2048;
+  constexpr int SLOT = 2 * HALF + (BUILD ? 2048 : 0) + (COORDS ? FI / 2 * 16 : 0);
+  __shared__ __align__(16) char ring0[SLOT];
+  __shared__ __align__(16) char ring1[SLOT];
+  __shared__ __align__(16) char ring2[SLOT];
+  __shared__ __align__(16) char ring3[SLOT];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (COORDS) {
+    for (int k = tid; k < FI / 2; k += WTR_THREADS) {
+      const float4 r = a.Bmat[k];
+      ((float4*)(ring0 + BROWS))[k] = r;
+      ((float4*)(ring1 + BROWS))[k] = r;
+      ((float4*)(ring2 + BROWS))[k] = r;
+      ((float4*)(ring3 + BROWS))[k] = r;
+    }
+  }
 
   const int64_t P = a.off[a.R];
   const int64_t n_tiles = (P + a.tile - 1) / a.tile;
@@ -338,26 +374,106 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   const int64_t b0 = (int64_t)blockIdx.x * a.kb;
   const int64_t nb2 = (nblk + 1) / 2 * 2;
   if (b0 >= nb2) return;
-  const int64_t b1 = b0 + a.kb < nb2 ? b0 + a.kb : nb2;
+  const int64_t b1 = b0 + ((b0 + a.kb < nb2 ? a.kb : nb2 - b0) + 3) / 4 * 4;
 
-  // DMA of block b into a ring slot: wave w copies delta chunk w and h chunk
-  // w; lane l's 16 bytes are the stash piece pi(l) of that chunk (pi: the
-  // upper half at point xor 4, an involution).  Blocks past the chunk's end
-  // get an empty buffer range: the copy writes zeros.
+  // Copies of block b into a ring slot.  Wave w: delta chunk w (DM 0), or the
+  // Swish derivative chunk w (DM 2); h chunk w (not COORDS); wave 0 also the
+  // mask words (DM 1) or the coordinates (COORDS), wave 1 dL/dz_o (DM 1, 2).
+  // A chunk's lane l gets the stash piece pi(l) (pi: the upper half at point
+  // xor 4, an involution).  Blocks past the chunk's end get an empty buffer
+  // range: the copy writes zeros.  Cache policy 2: streaming, read once.
   const int piece = lane < 32 ? lane : 32 + ((lane - 32) ^ 4);
   const uint32_t voff = lane_off((uint32_t)((w * 64 + piece) * 16));
+  const uint32_t voff16 = lane_off((uint32_t)(lane * 16)), voff4 = lane_off((uint32_t)(lane * 4));
   const char* stash = (const char*)a.stash;
+  const bool d_copy = DM != 1, h_copy = !COORDS;
+  const bool aux0 = (DM == 1 || COORDS) && w == 0, aux1 = DM != 0 && w == 1;
+  // copies per block issued by this wave
+  const int n_ops = (d_copy ? 1 : 0) + (h_copy ? 1 : 0) + (aux0 ? 1 : 0) + (aux1 ? 1 : 0);
   auto dma = [&](int64_t b, char* slot) {
     const bool ok = b < nblk;
-    const char* d = stash + (a.d_base + b * CH * 64) * 16;
-    const char* h = stash + (a.h_base + b * CH * 64) * 16;
-    const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(d, ok ? HALF : 0);
-    const __amdgpu_buffer_rsrc_t rh = buffer_rsrc(h, ok ? HALF : 0);
-    // cache policy 2: streaming (nt), the stash is read once
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rd, (lds_void*)(slot + w * 1024), 16, (int)voff, 0,
-                                             0, 2);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rh, (lds_void*)(slot + HALF + w * 1024), 16,
-                                             (int)voff, 0, 0, 2);
+    if (d_copy) {
+      const char* d = stash + ((DM == 2 ? a.m_base : a.d_base) + b * CH * 64) * 16;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(buffer_rsrc(d, ok ? HALF : 0),
+                                               (lds_void*)(slot + w * 1024), 16, (int)voff, 0,
+                                               0, 2);
+    }
+    if (h_copy) {
+      const char* h = stash + (a.h_base + b * CH * 64) * 16;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(buffer_rsrc(h, ok ? HALF : 0),
+                                               (lds_void*)(slot + HALF + w * 1024), 16,
+                                               (int)voff, 0, 0, 2);
+    }
+    if (aux0) {
+      // 64 mask chunks (one per lane of the block), or 32 points' coordinates
+      const char* m = COORDS ? stash + (a.h_base + b * 32) * 16 : stash + (a.m_base + b * 64) * 16;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(buffer_rsrc(m, ok ? (COORDS ? 512 : 1024) : 0),
+                                               (lds_void*)(slot + AUX), 16, (int)voff16, 0, 0,
+                                               2);
+    }
+    if (aux1) {
+      const char* o = stash + a.dob_base * 16 + b * 32 * 4;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(buffer_rsrc(o, ok ? 128 : 0),
+                                               (lds_void*)(slot + AUX + 1024), 4, (int)voff4, 0,
+                                               0, 2);
+    }
+  };
+
+  // Operands built in a slot from the copied sources (all threads).
+  auto build = [&](char* slot) {
+    if constexpr (DM == 2) {
+      // delta / w_o = dL/dz_o . swish'(z_L), rounded once, in place
+      const int c = tid >> 6, lam = tid & 63;
+      const int pnt = (lam < 32 ? lam : 32 + ((lam - 32) ^ 4)) & 31;
+      const float dob = ((const float*)(slot + AUX + 1024))[pnt];
+      bf16x8* q = (bf16x8*)(slot + c * 1024 + lam * 16);
+      const bf16x8 sd = *q;
+      typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2_t;
+      typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2_t;
+      bf16x8 r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x2_t v = {dob * (float)sd[2 * j], dob * (float)sd[2 * j + 1]};
+        const bf16x2_t b2 = __builtin_convertvector(v, bf16x2_t);
+        r[2 * j] = b2[0];
+        r[2 * j + 1] = b2[1];
+      }
+      *q = r;
+    } else if constexpr (DM == 1) {
+      // delta / w_o = dL/dz_o where the mask bit is set: the bits of slots 2j
+      // and 2j + 1 of chunk c are bits j and j + 16 of word c / 4 shifted by
+      // 4 (c mod 4), so (word >> j) & 0x10001 times the 16 bits of dL/dz_o is
+      // the packed pair
+      const int c = tid >> 6, lam = tid & 63;
+      const int L = lam < 32 ? lam : 32 + ((lam - 32) ^ 4);
+      const float dob = ((const float*)(slot + AUX + 1024))[L & 31];
+      const uint32_t dbits = __builtin_bit_cast(uint16_t, (__bf16)dob);
+      const uint32_t mw = ((const uint32_t*)(slot + AUX + L * 16))[c / 4] >> (4 * (c % 4));
+      u32x4 r;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) r[j] = ((mw >> j) & 0x10001u) * dbits;
+      *(u32x4*)(slot + c * 1024 + lam * 16) = r;
+    }
+    if constexpr (COORDS) {
+      // h_0 = [cos 2 pi u ; sin 2 pi u]: thread (c, lam, half) makes elements
+      // 4 half .. + 3 of cos chunk c < 8 and of sin chunk c + 8
+      const int c = tid >> 7, lam = (tid >> 1) & 63, half = tid & 1;
+      const int L = lam < 32 ? lam : 32 + ((lam - 32) ^ 4);
+      const float4 rc = ((const float4*)(slot + AUX))[L & 31];
+      typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4_t;
+      bf16x4_t cv, sv;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int f = feat(8 * c + 4 * half + i, L >> 5);
+        float s_, c_;
+        sincos_rev<PREC_BF16>(grff_phase(((const float4*)(slot + BROWS))[f], rc.x, rc.y, rc.z, rc.w),
+                              &s_, &c_);
+        cv[i] = (__bf16)c_;
+        sv[i] = (__bf16)s_;
+      }
+      *(bf16x4_t*)(slot + HALF + c * 1024 + lam * 16 + 8 * half) = cv;
+      *(bf16x4_t*)(slot + HALF + (c + 8) * 1024 + lam * 16 + 8 * half) = sv;
+    }
   };
 
   // operand addresses: wave w holds tiles (rb, cb) for rb in {2 (w / 4), +1},
@@ -385,6 +501,7 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   // K-step, Kahan-accumulates the block's sum, and the two K halves (lanes l
   // and l + 32) are added at the end
   const bool db_wave = (w & 3) == 0;
+
   f32x16 acc[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
@@ -392,13 +509,15 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
     for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
   float dbacc[2] = {0.f, 0.f}, dbcomp[2] = {0.f, 0.f};
 
-  auto step = [&](int64_t b, char* cur, char* nxt) {
-    // this wave's copies of block b are done (those of b + 1 and b + 2, two
-    // instructions each, may still run); the barrier makes every wave's
-    // copies visible and frees the slot block b - 1 was reduced from
-    wait_vm<4>();
+  // one block: copies of block b (copied blocks) or of b + 1 (built blocks)
+  // are done, the barrier publishes them (and the block built last step) and
+  // frees the slot of block b - 1; then the next copies, the next build, and
+  // the reduction of block b
+  auto step = [&](int64_t b, char* cur, char* nb, char* nxt) {
+    wait_vm_n(BUILD ? n_ops : 2 * n_ops);
     panel_barrier();
     dma(b + 3, nxt);
+    if (BUILD) build(nb);
     float sbk[2] = {0.f, 0.f};
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
@@ -434,15 +553,22 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   dma(b0, ring0);
   dma(b0 + 1, ring1);
   dma(b0 + 2, ring2);
-  // the split's block count is even (kb even; the last split ends at an even
-  // block): the ring turns in steps of four with a tail of two
+  if (BUILD) {
+    // the first block is built before the loop
+    wait_vm_n(2 * n_ops);
+    panel_barrier();
+    build(ring0);
+  }
+  // the ring turns in steps of four: the split's block count is rounded up to
+  // a multiple of four (only the chunk's last split can need it; the blocks
+  // added lie past the chunk's end, copy as zeros and add nothing), so every
+  // pass of the loop runs all four steps and the compiler's wait for a slot's
+  // copies at the top of the loop counts the copies issued after them
   for (int64_t b = b0; b < b1; b += 4) {
-    step(b, ring0, ring3);
-    step(b + 1, ring1, ring0);
-    if (b + 2 < b1) {
-      step(b + 2, ring2, ring1);
-      step(b + 3, ring3, ring2);
-    }
+    step(b, ring0, ring1, ring3);
+    step(b + 1, ring1, ring2, ring0);
+    step(b + 2, ring2, ring3, ring1);
+    step(b + 3, ring3, ring0, ring2);
   }
   // drain the copies issued past the split's end before the workgroup exits
   wait_vm<0>();
@@ -455,7 +581,8 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = 32 * rb + 8 * (r / 4) + 4 * hf + (r % 4);
-      out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] = acc[k][r];
+      out[a.w_off + (int64_t)row * FI + 32 * cb + (lane & 31)] =
+          DM ? acc[k][r] * a.wo[row] : acc[k][r];
     }
   }
   if (db_wave) {
@@ -465,7 +592,8 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
       // included
       const float own = dbacc[k] - dbcomp[k];
       const float other = __shfl_xor(own, 32);
-      if (lane < 32) out[a.b_off + 32 * (rb0 + k) + lane] = own + other;
+      const int f = 32 * (rb0 + k) + lane;
+      if (lane < 32) out[a.b_off + f] = DM ? (own + other) * a.wo[f] : own + other;
     }
   }
 }
@@ -492,8 +620,17 @@ static hipError_t wgrad_hidden(const WgArgs& a, int grid, hipStream_t st) {
 // Layer 1 (coordinates) always reads stashed delta blocks: its delta is the
 // last layer's only when L = 1, and then it is stashed.
 hipError_t launch_wgrad(int prec, int fi, int h, const WgArgs& a, int grid, hipStream_t st) {
-  if (prec == PREC_BF16 && fi == 256 && h == 256 && !a.coords && a.dmode == 0) {
-    hipLaunchKernelGGL(k_wgrad_tr, dim3(grid), dim3(WTR_THREADS), 0, st, a);
+  if (prec == PREC_BF16 && fi == 256 && h == 256) {
+    if (a.coords && a.dmode == 0)
+      hipLaunchKernelGGL((k_wgrad_tr<0, true>), dim3(grid), dim3(WTR_THREADS), 0, st, a);
+    else if (!a.coords && a.dmode == 0)
+      hipLaunchKernelGGL((k_wgrad_tr<0, false>), dim3(grid), dim3(WTR_THREADS), 0, st, a);
+    else if (!a.coords && a.dmode == 1)
+      hipLaunchKernelGGL((k_wgrad_tr<1, false>), dim3(grid), dim3(WTR_THREADS), 0, st, a);
+    else if (!a.coords && a.dmode == 2)
+      hipLaunchKernelGGL((k_wgrad_tr<2, false>), dim3(grid), dim3(WTR_THREADS), 0, st, a);
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
 #define X(I, HH)                                                                  \
