@@ -29,6 +29,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# per-step time statistics of each timed leg (median, p90, extremes)
+STEP_STATS = {}
+
+
 def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     """Times `steps` training steps (Adam included) after `warmup` untimed ones.
     Returns (ms per step, per-kernel times, the un-timed reference step's
@@ -74,16 +78,23 @@ def run_workload(name, prec, batch, steps, warmup, ws_bytes):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    # an event after every step (no synchronisation between steps): the
+    # per-step times give the median and p90 beside the mean
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     e0.record(st)
-    for _ in range(steps):
+    for i in range(steps):
         k += 1
         if jitter:
             ctx.set_sample_epoch(k)
         ctx.step(P, idx, meas, grad=grad, proj=proj, loss=loss, gnorm=gnorm,
                  adam=(m, v, 1e-3, 0.9, 0.999, 1e-8, k))
+        ev[i].record(st)
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    per = [e0.elapsed_time(ev[0])] + [ev[i - 1].elapsed_time(ev[i]) for i in range(1, steps)]
+    STEP_STATS[name] = dict(median_ms=float(np.median(per)), p90_ms=float(np.percentile(per, 90)),
+                            min_ms=float(min(per)), max_ms=float(max(per)))
     kern = {}
     for kind, kname in [(dinr.PROF_MLP_FWD, "mlp_fwd"), (dinr.PROF_MLP_BWD, "mlp_bwd"),
                         (dinr.PROF_MLP_FUSED, "mlp_fused"), (dinr.PROF_WGRAD, "wgrad"),
@@ -371,8 +382,8 @@ def paper_network(steps, warmup, ws, sub=1, jitter=0):
     out = dict(workload=f"paper network on the c2 geometry: {rays}, GRFF "
                         "2C=256 (sigma_s 0.5, sigma_t 0.1), 5 Swish layers of width 256, "
                         "linear output, BF16 MLP GEMMs",
-               ray_samples=P_pts, ms_per_step=ms, value=P_pts / (ms * 1e-3),
-               unit="ray-samples/s", status=status,
+               ray_samples=P_pts, ms_per_step=ms, step_ms_stats=STEP_STATS.get("paper"),
+               value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
                step_tflops=b.workload.mlp.flops_per_point() * P_pts / (ms * 1e-3) / 1e12,
                kernels={k: dict(ms_per_step=v["ms_per_step"],
                                 alg_tflops=alg[k] / (v["ms_per_step"] * 1e-3) / 1e12)
@@ -400,6 +411,7 @@ def cone_ragged(steps, warmup, ws):
                         "deg, 131072 rays x clamp(ceil(l*256), 32, 512) samples, GRFF 2C=256, "
                         "8 ReLU layers of width 256, softplus output, BF16, recomputing backward",
                rays=len(b.idx), ray_samples=P_pts, ms_per_step=ms,
+               step_ms_stats=STEP_STATS.get("c3"),
                value=P_pts / (ms * 1e-3), unit="ray-samples/s", status=status,
                step_tflops=f_all * P_pts / (ms * 1e-3) / 1e12,
                step_frac=f_all * P_pts / (ms * 1e-3) / PEAK["bf16"],
@@ -522,6 +534,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_bf16,
+        "step_ms_stats": STEP_STATS.get("c2"),
         "steps_per_s": 1e3 / ms_bf16,
         "higher_is_better": True,
         "scaling": "weak",
