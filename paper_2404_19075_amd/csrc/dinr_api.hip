@@ -59,6 +59,7 @@ struct Plan {
   int64_t h_base[MAX_LAYERS], d_base[MAX_LAYERS], a_base[MAX_LAYERS];
   int64_t dob_base = 0, m_base = 0, ring_blocks = 0;
   float* wpart = nullptr;
+  float* wstate = nullptr;  // running sums of the split partials over chunks
   float* opart = nullptr;
   double* lpart = nullptr;
   double* gn_part = nullptr;
@@ -151,12 +152,12 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   if (!A.ok) return fail(c, DINR_ENOMEM, "workspace budget too small for R=%lld", (long long)R);
   if (!adjoint) return DINR_OK;
 
-  // adjoint: split partials for the whole batch, output-layer partials per
-  // chunk, then as large a stash chunk as the remaining budget allows.
-  // points summed by one weight-gradient workgroup: 16,384 here (the partials
-  // are allocated for it); raised below once the chunk size is known
-  const int64_t k_split = 16384;
-  p->kb = k_split / 32;
+  // adjoint: split partials for one stash chunk, output-layer partials per
+  // chunk, then as large a stash chunk as the remaining budget allows.  A
+  // weight-gradient workgroup sums a split of 4,096 to 65,536 points, chosen
+  // below once the chunk size is known (the stash chunks are multiples of
+  // 16,384 points)
+  const int64_t ks_min = 4096, ks_max = 65536, k_chunk = 16384;
   // stash bytes per point: layer 1's input as the point's 4 coordinates (16
   // bytes), h_1 .. h_{L-1} and delta_1 .. delta_{L-1}; delta_L (L >= 2) as
   // dL/dz_o (4 bytes) and, ReLU, the last layer's mask bits (32 bytes per
@@ -179,10 +180,15 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
   p->ring_blocks = (group >= 2 && group <= 64 ? group : 1) * (c->tile / 32);
   const int64_t ring_chunks = swish ? (int64_t)(c->L - 1) * p->grid_mlp * p->ring_blocks *
                                           layer_chunks : 0;
-  const int64_t quantum = std::max<int64_t>(k_split, c->tile);  // both powers of two
+  const int64_t quantum = std::max<int64_t>(k_chunk, c->tile);  // both powers of two
   const int64_t pts_pad = std::max<int64_t>((p->points_max + quantum - 1) / quantum * quantum, quantum);
-  const int64_t total_splits = pts_pad / k_split;
-  p->wpart = A.take<float>((size_t)total_splits * c->nh);
+  // partials of one chunk: up to 2 n_cu splits (no more than one per 16,384
+  // points of the batch), or one per 65,536 points of the batch when that is
+  // more; the split size below keeps every chunk within this
+  const int64_t max_splits = std::max<int64_t>(std::min<int64_t>(2 * c->n_cu, pts_pad / k_chunk),
+                                               (pts_pad + ks_max - 1) / ks_max);
+  p->wpart = A.take<float>((size_t)max_splits * c->nh);
+  p->wstate = A.take<float>((size_t)2 * c->nh);
   p->gn_part = A.take<double>((size_t)((c->np + 255) / 256));
   if (!A.ok) return fail(c, DINR_ENOMEM, "workspace budget too small for the gradient partials");
   // try the whole batch in one chunk, then halve
@@ -205,13 +211,18 @@ static int plan_call(dinr_ctx* c, int64_t R, bool adjoint, Plan* p, Arena A) {
                   (long long)chunk);
     chunk = std::max<int64_t>(quantum, (chunk / 2 + quantum - 1) / quantum * quantum);
   }
-  // larger splits (up to 65,536 points) while every chunk still gives each
-  // compute unit a split: fewer partials to write and to combine
-  int64_t ks = k_split;
-  while (ks < 65536 && p->chunk_points % (2 * ks) == 0 && p->chunk_points / (2 * ks) >= c->n_cu)
+  // the largest split (a power of two, 4,096 to 65,536 points) that still
+  // gives each compute unit a split of the chunk, as long as the chunk's
+  // partials fit: fewer partials to write and to combine, and a full grid for
+  // small chunks.  The chunk's last split may be partial; at 65,536 points a
+  // chunk has at most pts_pad / 65,536 splits, so the loop ends within bounds
+  int64_t ks = ks_min;
+  while (ks < ks_max && (p->chunk_points / (2 * ks) >= c->n_cu ||
+                         (p->chunk_points + ks - 1) / ks > max_splits))
     ks *= 2;
   p->kb = ks / 32;
-  p->splits_per_chunk = p->chunk_points / ks;
+  p->splits_per_chunk = (p->chunk_points + ks - 1) / ks;
+  if (p->splits_per_chunk > max_splits) return fail(c, DINR_EINVAL, "split plan");
   // the Swish derivative ring (layers 1 .. L-1), then the stash region of each
   // layer: h blocks then delta blocks, in 16-byte chunks
   for (int l = 0; l + 1 < c->L; ++l)
@@ -356,7 +367,7 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       w.m_base = c->mlp.act == DINR_SWISH ? p.a_base[l] : p.m_base;
       w.wo = params + c->wo_off;
       w.wpart = p.wpart;
-      w.split_base = ch * p.splits_per_chunk;
+      w.split_base = 0;  // one chunk's partials, combined after its launches
       w.nh = c->nh;
       w.w_off = c->w_off[l];
       w.b_off = c->b_off[l];
@@ -364,31 +375,33 @@ static int enqueue_adjoint(dinr_ctx* c, const Plan& p, const float* params, cons
       ProfScope ps(c, DINR_PROF_WGRAD, st);
       HIPCHK(c, launch_wgrad(prec, l == 0 ? c->IN : c->H, c->H, w, (int)p.splits_per_chunk, st));
     }
+    RedArgs r{};
+    r.off = p.off;
+    r.R = p.R;
+    r.tile = c->tile;
+    r.chunk = ch;
+    r.chunk_points = p.chunk_points;
+    r.kb = p.kb;
+    r.first = ch == 0;
+    r.last = ch + 1 == p.n_chunks;
+    r.wpart = p.wpart;
+    r.state = p.wstate;
+    r.nh = c->nh;
+    r.opart = p.opart;
+    r.n_opart = p.n_chunks * p.grid_mlp;
+    r.no = c->H + 1;
+    r.np = c->np;
+    r.grad = grad;
+    r.gn_part = p.gn_part;
+    if (r.last && (mode == MODE_FUSED || mode == MODE_GROUP)) {
+      // the grouped step computed every projection's loss term in the kernel
+      ProfScope ps(c, DINR_PROF_LOSS, st);
+      HIPCHK(c, launch_loss_fused(p.rays, meas, mode == MODE_GROUP ? 0 : p.R, p.lpart,
+                                  p.n_chunks * p.grid_mlp, proj, p.lsum, c->d_scal, p.Rp, st));
+    }
+    ProfScope ps(c, DINR_PROF_REDUCE, st);
+    HIPCHK(c, launch_reduce(r, c->d_scal + 1, gnorm_out, st));
   }
-  RedArgs r{};
-  r.off = p.off;
-  r.R = p.R;
-  r.tile = c->tile;
-  r.n_chunks = p.n_chunks;
-  r.chunk_points = p.chunk_points;
-  r.kb = p.kb;
-  r.splits_per_chunk = p.splits_per_chunk;
-  r.wpart = p.wpart;
-  r.nh = c->nh;
-  r.opart = p.opart;
-  r.n_opart = p.n_chunks * p.grid_mlp;
-  r.no = c->H + 1;
-  r.np = c->np;
-  r.grad = grad;
-  r.gn_part = p.gn_part;
-  if (mode == MODE_FUSED || mode == MODE_GROUP) {
-    // the grouped step computed every projection's loss term in the kernel
-    ProfScope ps(c, DINR_PROF_LOSS, st);
-    HIPCHK(c, launch_loss_fused(p.rays, meas, mode == MODE_GROUP ? 0 : p.R, p.lpart,
-                                p.n_chunks * p.grid_mlp, proj, p.lsum, c->d_scal, p.Rp, st));
-  }
-  ProfScope ps(c, DINR_PROF_REDUCE, st);
-  HIPCHK(c, launch_reduce(r, c->d_scal + 1, gnorm_out, st));
   return DINR_OK;
 }
 

@@ -138,12 +138,18 @@ struct WgArgs {
   int layer;
 };
 
+// One launch per stash chunk, in chunk order: the chunk's split partials are
+// added to a running compensated sum (state: sums then compensations, nh
+// floats each), so the result is that of one pass over every split in order.
 struct RedArgs {
   const int64_t* off;
   int64_t R;
   int tile;
-  int64_t n_chunks, chunk_points, kb, splits_per_chunk;
-  const float* wpart;
+  int64_t chunk, chunk_points, kb;
+  int first, last;             // first chunk: the sums start at zero; last:
+                               // grad, the output-layer sums and grad^2 blocks
+  const float* wpart;          // [splits of this chunk][nh]
+  float* state;                // [2][nh]
   int64_t nh;
   const float* opart;
   int64_t n_opart, no;

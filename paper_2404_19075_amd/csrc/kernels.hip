@@ -364,6 +364,8 @@ __global__ __launch_bounds__(LOSS_T) void k_loss_total(const double* __restrict_
 
 // grad[k] = compensated sum over valid split partials (hidden layers) or over
 // the per-workgroup output-layer partials; per-block FP64 sums of grad^2.
+// Hidden-layer sums run over the stash chunks, one launch each, with the
+// running sum and its compensation kept in a.state between launches.
 __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   __shared__ double s[256];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -371,23 +373,45 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   if (k < a.np) {
     float sum = 0.f, comp = 0.f;
     if (k < a.nh) {
+      if (!a.first) {
+        sum = a.state[k];
+        comp = a.state[a.nh + k];
+      }
       const int64_t P = a.off[a.R];
       const int64_t n_tiles = (P + a.tile - 1) / a.tile;
       const int64_t pend = n_tiles * a.tile;
-      for (int64_t c = 0; c < a.n_chunks; ++c) {
-        const int64_t p0 = c * a.chunk_points;
-        if (p0 >= pend) break;
+      const int64_t p0 = a.chunk * a.chunk_points;
+      if (p0 < pend) {
         const int64_t pe = (pend < p0 + a.chunk_points) ? pend : p0 + a.chunk_points;
         const int64_t nblk = (pe - p0) / 32;
         const int64_t nsp = (nblk + a.kb - 1) / a.kb;
-        for (int64_t i = 0; i < nsp; ++i) {
-          const float y = a.wpart[(c * a.splits_per_chunk + i) * a.nh + k] - comp;
+        // eight loads in flight, then the eight steps in split order
+        const float* src = a.wpart + k;
+        int64_t i = 0;
+        for (; i + 8 <= nsp; i += 8) {
+          float x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = __builtin_nontemporal_load(src + (i + u) * a.nh);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const float y = x[u] - comp;
+            const float t = sum + y;
+            comp = (t - sum) - y;
+            sum = t;
+          }
+        }
+        for (; i < nsp; ++i) {
+          const float y = src[i * a.nh] - comp;
           const float t = sum + y;
           comp = (t - sum) - y;
           sum = t;
         }
       }
-    } else {
+      if (!a.last) {
+        a.state[k] = sum;
+        a.state[a.nh + k] = comp;
+      }
+    } else if (a.last) {
       const int64_t j = k - a.nh;
       for (int64_t i = 0; i < a.n_opart; ++i) {
         const float y = a.opart[i * a.no + j] - comp;
@@ -396,9 +420,13 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
         sum = t;
       }
     }
-    a.grad[k] = sum;
-    sq = (double)sum * (double)sum;
+    if (a.last) {
+      a.grad[k] = sum;
+      sq = (double)sum * (double)sum;
+    }
   }
+  if (!a.last) return;  // uniform over the grid
+
   s[threadIdx.x] = sq;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -567,8 +595,9 @@ hipError_t launch_loss_fused(const RayRec* rays, const float* meas, int64_t R, c
 hipError_t launch_reduce(const RedArgs& a, double* gnorm_ws, double* gnorm_out, hipStream_t st) {
   const unsigned nblk = (unsigned)((a.np + 255) / 256);
   hipLaunchKernelGGL(k_reduce, dim3(nblk), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(256), 0, st, a.gn_part, (int64_t)nblk, gnorm_ws,
-                     gnorm_out);
+  if (a.last)
+    hipLaunchKernelGGL(k_gnorm, dim3(1), dim3(256), 0, st, a.gn_part, (int64_t)nblk, gnorm_ws,
+                       gnorm_out);
   return hipGetLastError();
 }
 
