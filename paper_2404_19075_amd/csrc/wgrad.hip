@@ -386,10 +386,23 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   const uint32_t voff = lane_off((uint32_t)((w * 64 + piece) * 16));
   const uint32_t voff16 = lane_off((uint32_t)(lane * 16)), voff4 = lane_off((uint32_t)(lane * 4));
   const char* stash = (const char*)a.stash;
-  const bool d_copy = DM != 1, h_copy = !COORDS;
+  constexpr bool d_copy = DM != 1, h_copy = !COORDS;
   const bool aux0 = (DM == 1 || COORDS) && w == 0, aux1 = DM != 0 && w == 1;
-  // copies per block issued by this wave
-  const int n_ops = (d_copy ? 1 : 0) + (h_copy ? 1 : 0) + (aux0 ? 1 : 0) + (aux1 ? 1 : 0);
+  // Copies per block: N_MIN by the waves without an auxiliary copy, N_MIN + 1
+  // by the one or two waves with one, issued in the order delta, h, aux.  The
+  // waits below are compile-time constants, the same for every wave (a wait
+  // chosen per wave at run time makes the compiler add waits of its own before
+  // the operand reads).  Blocks of copies only (DM 0, no auxiliary copies):
+  // before step b at most 2 N_MIN copies, blocks b + 1 and b + 2, are in
+  // flight, so block b has landed.  Built blocks: at most N_MIN + 1, that is
+  // block b + 2's copies and, in the waves with N_MIN copies, the last of
+  // block b + 1's (h for DM 1 and 2, delta for COORDS: neither is read by
+  // block b + 1's build), so that build finds its auxiliary copies and, DM 2,
+  // the delta chunk it rescales in place (copied by the same wave), and block
+  // b's copies have all landed.  Before the first build: at most 2 N_MIN, all
+  // from blocks b0 + 1 and b0 + 2 in every wave, so block b0 has landed.
+  constexpr int N_MIN = (d_copy ? 1 : 0) + (h_copy ? 1 : 0);
+  constexpr int WAIT_STEP = BUILD ? N_MIN + 1 : 2 * N_MIN, WAIT_FIRST = 2 * N_MIN;
   auto dma = [&](int64_t b, char* slot) {
     const bool ok = b < nblk;
     if (d_copy) {
@@ -514,7 +527,7 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   // frees the slot of block b - 1; then the next copies, the next build, and
   // the reduction of block b
   auto step = [&](int64_t b, char* cur, char* nb, char* nxt) {
-    wait_vm_n(BUILD ? n_ops : 2 * n_ops);
+    wait_vm<WAIT_STEP>();
     panel_barrier();
     dma(b + 3, nxt);
     if (BUILD) build(nb);
@@ -555,7 +568,7 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   dma(b0 + 2, ring2);
   if (BUILD) {
     // the first block is built before the loop
-    wait_vm_n(2 * n_ops);
+    wait_vm<WAIT_FIRST>();
     panel_barrier();
     build(ring0);
   }
