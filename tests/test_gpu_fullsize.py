@@ -109,12 +109,22 @@ def _sparse_step_check(ctx, w, b, prec, K, epoch, min_chunks, seed):
 
 def test_fullsize_c2_gradient_vs_oracle():
     """c2 as the benchmark times it: 65,536 rays x 256 samples, BF16, the
-    one-pass step with the whole stash in one chunk (1,024 weight-gradient
-    splits per layer)."""
+    one-pass step with the whole stash in one chunk (256 weight-gradient
+    splits of 65,536 points per layer)."""
     w = S.workload("c2")
     b = S.make_batch(w)
     log("full c2 vs oracle")
     sparse_step_check(w, b, BF16, ws=120 << 30, seed=1)
+
+
+def test_fullsize_c2_small_workspace_many_chunks():
+    """c2 at full size in a 6 GiB workspace: the stash is held in 16 chunks of
+    about a million points, each reduced in splits of 4,096 points, and the
+    per-parameter compensated sums carry from chunk to chunk."""
+    w = S.workload("c2")
+    b = S.make_batch(w)
+    log("full c2 in 6 GiB vs oracle")
+    sparse_step_check(w, b, BF16, ws=6 << 30, min_chunks=8, seed=6)
 
 
 def test_fullsize_c1_fp32_gradient_vs_oracle_chunked():
