@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"bf16": 2.5e15, "fp32": 157.3e12}  # dense matrix-core FLOP/s, MI355X datasheet
+PEAK_HBM = 8.0e12  # B/s, MI355X datasheet
 
 
 def log(*a):
@@ -352,6 +353,20 @@ def stream_rates(kern, R, D2, points, tile=256):
     return out
 
 
+def wgrad_stash_bytes(spec, P_pts, elem=2):
+    """Bytes the weight-gradient kernels of one BF16 step read: every byte of
+    the adjoint's stash once -- layer 1's point coordinates (16 B) and delta_1,
+    h_l and delta_l for the hidden layers, and for the last layer h_{L-1} with
+    dL/dz_o (4 B) and the ReLU mask words (one bit per unit) or the Swish
+    derivatives -- plus the split partials each launch writes (not counted:
+    0.5 % at c2)."""
+    hb = spec.width * elem
+    L = spec.depth
+    per = 16 + (L - 1) * hb + (L - 1) * hb + 4
+    per += spec.width // 8 if spec.act == 0 else hb
+    return per * P_pts
+
+
 def alg_flops(spec, P_pts):
     """Algorithmic FLOP per step of each kernel class: the forward GEMMs, the
     adjoint's input-gradient GEMMs (a recomputing backward kernel's repeat of
@@ -513,6 +528,14 @@ def main():
     roof["measured_peak_tflops"] = probe
     roof["frac_of_measured_peak"] = roof["achieved"] / max(probe.values())
     roof["traffic"] = traffic_from_profile(dom)
+    # the weight-gradient kernels, bound by HBM: the stash bytes they read per
+    # step over their HIP-event time
+    if "wgrad" in kern:
+        wb = wgrad_stash_bytes(spec, P_pts)
+        wr = wb / (kern["wgrad"]["ms_per_step"] * 1e-3)
+        roof["wgrad_hbm"] = dict(bound="hbm", achieved=wr / 1e9, peak=PEAK_HBM / 1e9,
+                                 unit="GB/s", frac=wr / PEAK_HBM, bytes_per_step=wb,
+                                 launches_per_step=kern["wgrad"]["launches_per_step"])
     loads = tuple(float(x) for x in args.serving_loads.split(","))
     serve = None if args.no_serving else serving(batch, trained, n_req=args.serving_requests,
                                                  rates=loads)
