@@ -344,24 +344,20 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   constexpr bool BUILD = DM != 0 || COORDS;
   constexpr int HALF = CH * 1024;                // delta (or h) bytes of one block
   constexpr int AUX = 2 * HALF;                  // mask words or coordinates (1 KB), dL/dz_o
-  // COORDS: a copy of the GRFF rows in every slot, never a copy target.  (Kept
-  // in an array of its own, the rows' reads would wait for every copy in
-  // flight: the compiler cannot tell that array from the copies' targets.)
-  constexpr int BROWS = AUX + 2048;
-  constexpr int SLOT = 2 * HALF + (BUILD ? 2048 : 0) + (COORDS ? FI / 2 * 16 : 0);
+  constexpr int SLOT = 2 * HALF + (BUILD ? 2048 : 0);
   __shared__ __align__(16) char ring0[SLOT];
   __shared__ __align__(16) char ring1[SLOT];
   __shared__ __align__(16) char ring2[SLOT];
   __shared__ __align__(16) char ring3[SLOT];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // COORDS: the GRFF rows of the four features this thread encodes, the same
+  // for every block
+  float4 brow[4];
   if (COORDS) {
-    for (int k = tid; k < FI / 2; k += WTR_THREADS) {
-      const float4 r = a.Bmat[k];
-      ((float4*)(ring0 + BROWS))[k] = r;
-      ((float4*)(ring1 + BROWS))[k] = r;
-      ((float4*)(ring2 + BROWS))[k] = r;
-      ((float4*)(ring3 + BROWS))[k] = r;
-    }
+    const int lam = (tid >> 1) & 63;
+    const int L = lam < 32 ? lam : 32 + ((lam - 32) ^ 4);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) brow[i] = a.Bmat[feat(8 * (tid >> 7) + 4 * (tid & 1) + i, L >> 5)];
   }
 
   const int64_t P = a.off[a.R];
@@ -470,17 +466,16 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
     if constexpr (COORDS) {
       // h_0 = [cos 2 pi u ; sin 2 pi u]: thread (c, lam, half) makes elements
       // 4 half .. + 3 of cos chunk c < 8 and of sin chunk c + 8
-      const int c = tid >> 7, lam = (tid >> 1) & 63, half = tid & 1;
+      const int lam = (tid >> 1) & 63;
       const int L = lam < 32 ? lam : 32 + ((lam - 32) ^ 4);
+      const int c = tid >> 7, half = tid & 1;
       const float4 rc = ((const float4*)(slot + AUX))[L & 31];
       typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4_t;
       bf16x4_t cv, sv;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int f = feat(8 * c + 4 * half + i, L >> 5);
         float s_, c_;
-        sincos_rev<PREC_BF16>(grff_phase(((const float4*)(slot + BROWS))[f], rc.x, rc.y, rc.z, rc.w),
-                              &s_, &c_);
+        sincos_rev<PREC_BF16>(grff_phase(brow[i], rc.x, rc.y, rc.z, rc.w), &s_, &c_);
         cv[i] = (__bf16)c_;
         sv[i] = (__bf16)s_;
       }
