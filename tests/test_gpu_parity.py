@@ -659,10 +659,10 @@ def paper_sampling(w, D=2, n=256, jitter=1, seed=31):
                                                                jitter=jitter, seed=seed))
 
 
-def step_kinds(w, b, prec, recompute=False, epoch=None):
+def step_kinds(w, b, prec, recompute=False, epoch=None, ws_bytes=2 << 30):
     """run_step plus the launches of each MLP kernel class it made."""
     from paper_2404_19075_amd import dinr
-    ctx = make_ctx(w, b.B, prec, recompute=recompute)
+    ctx = make_ctx(w, b.B, prec, ws_bytes=ws_bytes, recompute=recompute)
     if epoch is not None:
         ctx.set_sample_epoch(epoch)
     ctx.profile(True)
@@ -711,6 +711,33 @@ def test_grouped_one_pass_step_paper_sampling(prec):
     assert ep <= TOL_PROJ[prec] and el <= TOL_LOSS[prec]
     check_grad(w, o1["grad"], grad, TOL_GRAD[prec], f"grouped paper prec={prec}")
     assert o1["status"] == 0
+
+
+def test_grouped_one_pass_step_paper_sampling_chunked():
+    """As above (BF16) in a 1 GiB workspace, which holds the per-workgroup
+    derivative ring and half of the stash: the grouped one-pass step runs in
+    two or more stash chunks, the weight-gradient partials of each chunk are
+    folded into the running compensated sums before the next, and the result
+    matches the single-chunk step (projections bit for bit, gradient to
+    rounding) and the oracle."""
+    w = paper_sampling(small_workload("paper", 160))
+    b = S.make_batch(w)
+    log("test_grouped_one_pass_step_paper_sampling_chunked")
+    o1 = step_kinds(w, b, BF16, epoch=7)
+    o2 = step_kinds(w, b, BF16, epoch=7, ws_bytes=1 << 30)
+    log(f"  kernels: one chunk {o1['kinds']}, small workspace {o2['kinds']}")
+    assert o1["kinds"]["one_pass"] == 1 and o1["kinds"]["bwd"] == 0
+    assert o2["kinds"]["one_pass"] >= 2 and o2["kinds"]["bwd"] == 0
+    eg = rel(o2["grad"], o1["grad"])
+    log(f"  chunked vs one chunk: grad rel diff {eg:.2e}")
+    assert np.array_equal(o1["proj"], o2["proj"])
+    assert eg <= 1e-6
+    assert abs(o1["loss"] - o2["loss"]) <= 1e-12 * o1["loss"]
+    spe = dataclasses.replace(w.sampling, epoch=7)
+    loss, grad, proj = O.step(w.geom, w.mlp, spe, b.B, b.params, b.idx, b.meas)
+    assert rel(o2["proj"], proj) <= TOL_PROJ[BF16]
+    check_grad(w, o2["grad"], grad, TOL_GRAD[BF16], "grouped paper chunked")
+    assert o2["status"] == 0
 
 
 def test_grouped_one_pass_step_edges():
