@@ -524,8 +524,18 @@ __global__ __launch_bounds__(WTR_THREADS) void k_wgrad_tr(WgArgs a) {
   auto step = [&](int64_t b, char* cur, char* nb, char* nxt) {
     wait_vm<WAIT_STEP>();
     panel_barrier();
-    dma(b + 3, nxt);
-    if (BUILD) build(nb);
+    // the work every wave must finish before the next barrier runs at a raised
+    // wave priority: the next copies (blocks of copies only) or the next build
+    if (BUILD) {
+      dma(b + 3, nxt);
+      __builtin_amdgcn_s_setprio(2);
+      build(nb);
+      __builtin_amdgcn_s_setprio(0);
+    } else {
+      __builtin_amdgcn_s_setprio(2);
+      dma(b + 3, nxt);
+      __builtin_amdgcn_s_setprio(0);
+    }
     float sbk[2] = {0.f, 0.f};
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
